@@ -1,0 +1,230 @@
+"""Benchmark of the Wilson-Dirac operator on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32] [--c12]
+
+A step is one application of dslash_apply (D = (4+m) - H/2, periodic, m = 0.1)
+to a Gaussian spinor with random SU(3) links on the 32^3 x 64 lattice
+(2,097,152 sites), inputs already packed in HBM. Prints one JSON line with
+GFlop/s (1320 flop/site), the HBM roofline fraction on compulsory bytes, a
+sampled parity check against the CPU oracle, and the oracle's own time on the
+host as the CPU baseline.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = "dslash GFlop/s & % HBM peak; mixed-prec CG solves/s, p50/p99 latency"
+FLOPS_PER_SITE = 1320
+HBM_PEAK_GBS = 8000.0
+DIMS = (32, 32, 32, 64)
+CONFIG_INDEX = 2          # seeds of the production-lattice configuration
+
+# Compulsory HBM bytes per site: 4 links + spinor in + spinor out.
+def compulsory_bytes(prec: str, c12: bool) -> int:
+    real = 8 if prec == "fp64" else 4
+    return real * (4 * (12 if c12 else 18) + 24 + 24)
+
+
+# HBM traffic of the dslash kernel measured with rocprofv3 --pmc (FETCH_SIZE,
+# WRITE_SIZE), scaled by the same counters on a plain copy of known size; valid
+# only for the kernel sources it was measured on (hash below), else null.
+TRAFFIC = {}
+KERNEL_SOURCES = ["paper_1901_07294_amd/csrc/dslash.hip", "paper_1901_07294_amd/csrc/fields.h",
+                  "paper_1901_07294_amd/csrc/cplx.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def parse(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--c12", action="store_true", help="12-real link compression")
+    ap.add_argument("--dims", type=str, default=",".join(map(str, DIMS)))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the secondary precision/compression measurements")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain device copy of known size (PMC calibration)")
+    return ap.parse_args(argv)
+
+
+def copy_calibration(torch, nbytes=1 << 30, reps=5):
+    """Plain device-to-device copy of nbytes, for counter calibration and the
+    achievable-bandwidth ceiling. Returns GB/s (read + write bytes)."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    return 2 * nbytes / t / 1e9
+
+
+def time_applies(torch, w, g, src, dst, mass, steps, warmup):
+    for _ in range(warmup):
+        w.dslash_apply(g.handle, mass, src, dst, g.prec)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        w.dslash_apply(g.handle, mass, src, dst, g.prec)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per apply
+
+
+def main(argv=None):
+    args = parse(argv)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path is a single-GPU whole-lattice operator)", file=sys.stderr)
+        return 2
+
+    import torch
+    import lattice_inputs as li
+    import paper_1901_07294_amd.wilson as w
+    from paper_1901_07294_amd.buffers import DeviceGauge
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+
+    if args.copy_calib:
+        gbs = copy_calibration(torch)
+        print(json.dumps({"copy_calibration_bytes": 1 << 30, "copy_gbs": round(gbs, 1)}))
+        return 0
+
+    dims = tuple(int(v) for v in args.dims.split(","))
+    V = li.volume(dims)
+    mass = 0.1
+    prec_id = {"fp64": w.WD_FP64, "fp32": w.WD_FP32}
+    print(f"[bench] generating inputs dims={dims}", file=sys.stderr, flush=True)
+    t0 = time.time()
+    U = li.random_gauge(dims, li.seed_gauge(CONFIG_INDEX))
+    psi = li.gaussian_spinor(dims, li.seed_spinor(CONFIG_INDEX))
+    print(f"[bench] inputs ready in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    Ud = torch.from_numpy(U).to("cuda")
+    psid = torch.from_numpy(psi).to("cuda")
+
+    def measure(prec: str, c12: bool, steps: int, warmup: int):
+        g = DeviceGauge(Ud, prec_id[prec], c12)
+        src = g.spinor()
+        dst = g.spinor()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        w.wd_spinor_import(g.handle, psid, g.prec, 1, src)
+        e1.record()
+        torch.cuda.synchronize()
+        pack_ms = e0.elapsed_time(e1)
+        ms = time_applies(torch, w, g, src, dst, mass, steps, warmup)
+        return g, src, dst, ms, pack_ms
+
+    print(f"[bench] timing {args.prec} c12={args.c12}", file=sys.stderr, flush=True)
+    g, src, dst, ms, pack_ms = measure(args.prec, args.c12, args.steps, args.warmup)
+    t_s = ms / 1e3
+    gflops = FLOPS_PER_SITE * V / t_s / 1e9
+    cbytes = compulsory_bytes(args.prec, args.c12)
+    achieved = cbytes * V / t_s / 1e9
+
+    # parity on sampled sites (outside the timed region)
+    import oracle
+    out = g.unpack(dst).reshape(-1, 4, 3)
+    rng = np.random.default_rng(7)
+    sites = rng.choice(V, min(V, 2048), replace=False)
+    ref = oracle.dslash_sites(U, psi, mass, sites)
+    parity = float(np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref))
+    tol = 1e-13 if args.prec == "fp64" else 1e-6
+    del g, src, dst
+
+    variants = {}
+    if not args.no_variants:
+        for p, c in (("fp64", True), ("fp32", False), ("fp32", True)):
+            if (p, c) == (args.prec, args.c12):
+                continue
+            gv, sv, dv, msv, _ = measure(p, c, max(20, args.steps // 4), 5)
+            variants[f"{p}{'_c12' if c else ''}"] = {
+                "ms_per_apply": round(msv, 5),
+                "gflops": round(FLOPS_PER_SITE * V / (msv / 1e3) / 1e9, 1),
+                "pct_hbm_peak": round(100 * compulsory_bytes(p, c) * V / (msv / 1e3) / 1e9
+                                      / HBM_PEAK_GBS, 2)}
+            del gv, sv, dv
+    copy_gbs = copy_calibration(torch)
+
+    workload = "wilson_dslash_" + "x".join(map(str, dims))
+    key = f"{workload}_{args.prec}{'_c12' if args.c12 else ''}"
+    traffic = None
+    rec = TRAFFIC.get(key)
+    if rec and rec["source_sha"] == kernel_source_hash():
+        traffic = rec["bytes_per_launch"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle (one full application)", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        oracle.dslash(U, psi, mass)
+        tc = time.perf_counter() - t0
+        cpu = {"value": round(FLOPS_PER_SITE * V / tc / 1e9, 4), "unit": "GFlop/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"one full FP64 application on the {'x'.join(map(str, dims))} lattice "
+                         f"({tc:.1f} s, numpy, single thread, {os.cpu_count()} host cores visible)"}
+
+    line = {
+        "metric": METRIC,
+        "value": round(gflops, 1),
+        "unit": "GFlop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f32",
+        "data": "synthetic (seeded random SU(3) links, Gaussian spinor)",
+        "config": {"workload": workload, "dims": list(dims), "prec": args.prec,
+                   "links": "12-real" if args.c12 else "full", "mass": mass,
+                   "gauge": "random SU(3)", "boundary": "periodic"},
+        "pct_hbm_peak": round(100 * achieved / HBM_PEAK_GBS, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": cbytes * V},
+        "parity": {"rel_err": parity, "tol": tol, "sites": int(len(sites)), "ok": parity <= tol},
+        "pack_ms": round(pack_ms, 4),
+        "copy_ceiling_gbs": round(copy_gbs, 1),
+        "variants": variants,
+        "kernel_source_sha": kernel_source_hash(),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0 if parity <= tol else 3
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,146 @@
+/*
+ * wilson.h -- C ABI of the MI355X (gfx950) Wilson-Dirac operator library.
+ *
+ * The library applies the Wilson-Dirac operator of lattice QCD with Wilson
+ * fermions on one GPU's whole periodic 4D lattice:
+ *
+ *   D psi(x) = (4+m) psi(x)
+ *              - 1/2 sum_mu [ (1-gamma_mu) U_mu(x) psi(x+mu)
+ *                             + (1+gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
+ *
+ * The sum is the hopping term of eq. (1) (Sec. II-A of Meyer et al., "SVE-
+ * enabling Lattice QCD Codes") up to the sign convention of gamma_mu; the two
+ * conventions are exchanged by gamma5 conjugation, so eq. (1)'s D_h equals
+ * 2(4+m) - 2 gamma5 D gamma5. psi carries spin (4) x colour (3) complex
+ * components per site, U_mu(x) is an SU(3) matrix on the link x -> x+mu
+ * (Sec. II-A), gamma_mu are the DeGrand-Rossi Dirac matrices, mu = 0,1,2,3 is
+ * x,y,z,t, and all four directions are periodic.
+ *
+ * Conventions shared by every entry point:
+ *   dims      int32_t[4] = {X, Y, Z, T}, each >= 1, with V = X*Y*Z*T < 2^31 / 12.
+ *             The canonical site index is x + X*(y + Y*(z + Z*t)) (x fastest).
+ *   canonical complex128 (interleaved re, im) arrays in device memory:
+ *             spinor psi[nrhs][T][Z][Y][X][spin 4][colour 3]
+ *             gauge  U  [T][Z][Y][X][mu 4][row 3][col 3]
+ *   packed    the library's own device layouts (structure of arrays with the
+ *             site index fastest). Their size is given by wd_spinor_bytes /
+ *             wd_gauge_bytes; their contents are private to the library.
+ *   memory    the caller allocates and frees every device buffer; the library
+ *             never frees caller memory and allocates no device memory of
+ *             its own in the apply calls.
+ *   streams   every device call is asynchronous on the given stream (0 = the
+ *             null stream) unless stated otherwise.
+ *   errors    a negative wd_status. Argument errors are detected on the host
+ *             before any launch; launch failures return WD_ERR_DEVICE;
+ *             faults inside a kernel surface at the next synchronising call.
+ *             wd_last_error() describes the last failure of this thread.
+ *             Device pointers are checked with the HIP runtime: a host
+ *             pointer, a pointer on another device, or a buffer that ends
+ *             before the bytes the call needs is rejected with
+ *             WD_ERR_INVALID_ARG. No C++ exception crosses this interface.
+ */
+#ifndef WILSON_H
+#define WILSON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WD_ABI_VERSION 1
+
+#if defined(__GNUC__)
+#define WD_API __attribute__((visibility("default")))
+#else
+#define WD_API
+#endif
+
+typedef enum wd_status {
+  WD_OK = 0,
+  WD_PENDING = 1,
+  WD_ERR_INVALID_ARG = -1,
+  WD_ERR_SHAPE = -2,
+  WD_ERR_UNSUPPORTED = -3,
+  WD_ERR_NOMEM = -4,
+  WD_ERR_DEVICE = -5,
+  WD_ERR_NOT_CONVERGED = -6,
+  WD_ERR_NUMERIC = -7,
+  WD_ERR_UNKNOWN_TICKET = -8,
+  WD_ERR_CANCELLED = -9,
+  WD_ERR_INTERNAL = -10
+} wd_status;
+
+/* Storage and arithmetic precision of a packed field.
+ * WD_FP64: binary64 storage and arithmetic. WD_FP32: binary32 storage and
+ * arithmetic. */
+typedef enum wd_prec { WD_FP64 = 0, WD_FP32 = 1, WD_FP16 = 2 } wd_prec;
+
+/* flags of dslash_apply / dslash_apply_multi */
+#define WD_FLAG_GAMMA5 1 /* return gamma5 D psi (the Hermitian Q = gamma5 D) */
+
+typedef struct wd_gauge wd_gauge; /* opaque handle, owned by the library */
+
+/* Version of this interface (WD_ABI_VERSION of the built library). */
+WD_API int wd_abi_version(void);
+
+/* Text of the last error on the calling thread; empty if none. The pointer
+ * stays valid until the next call into the library on this thread. */
+WD_API const char* wd_last_error(void);
+
+/* Bytes of a packed spinor buffer holding nrhs fields of precision prec on a
+ * lattice of extents dims (Sec. II-A: 12 complex numbers per site). Returns 0
+ * for invalid arguments (bad dims, nrhs < 0, unknown precision). */
+WD_API size_t wd_spinor_bytes(const int32_t dims[4], int32_t prec, int32_t nrhs);
+
+/* Bytes of a packed gauge buffer (Sec. II-A: one SU(3) matrix per site and
+ * direction). compress12 != 0 stores only the first two rows of each link
+ * (12 reals); the third row is rebuilt as conj(row0 x row1), exact for SU(3).
+ * Returns 0 for invalid arguments. */
+WD_API size_t wd_gauge_bytes(const int32_t dims[4], int32_t prec, int32_t compress12);
+
+/* Packs a canonical complex128 gauge field U_canon_dev into dst_dev (at least
+ * wd_gauge_bytes(dims, prec, compress12) bytes, caller-owned, must outlive the
+ * handle) and returns a handle in *out. The pack is enqueued on stream; the
+ * handle may be used at once on the same stream. The canonical buffer is not
+ * kept. With compress12 the input links must be SU(3) (unitary, det 1) for
+ * the third row to be rebuilt exactly. Precisions: WD_FP64, WD_FP32.
+ * Errors: WD_ERR_INVALID_ARG (pointers, out == NULL), WD_ERR_SHAPE (dims),
+ * WD_ERR_UNSUPPORTED (precision), WD_ERR_DEVICE (launch). */
+WD_API int wd_gauge_import(const int32_t dims[4], const void* U_canon_dev, int32_t prec,
+                    int32_t compress12, void* dst_dev, size_t dst_bytes,
+                    hipStream_t stream, wd_gauge** out);
+
+/* Releases a handle (host memory only; never frees dst_dev). NULL is a no-op.
+ * The caller must not release a handle still used by enqueued work. */
+WD_API int wd_gauge_release(wd_gauge* g);
+
+/* Packs nrhs canonical complex128 spinor fields (canon_dev, layout above) into
+ * dst_dev (wd_spinor_bytes(dims of g, prec, nrhs) bytes) in precision prec,
+ * which must equal the precision of g. Enqueued on stream. */
+WD_API int wd_spinor_import(const wd_gauge* g, const void* canon_dev, int32_t prec, int32_t nrhs,
+                     void* dst_dev, hipStream_t stream);
+
+/* Inverse of wd_spinor_import: unpacks nrhs packed fields src_dev into
+ * canonical complex128 canon_dev. Enqueued on stream. */
+WD_API int wd_spinor_export(const wd_gauge* g, const void* src_dev, int32_t prec, int32_t nrhs,
+                     void* canon_dev, hipStream_t stream);
+
+/* out = D(mass) in (eq. (1) of Sec. II-A in the (4+m) - H/2 normalisation,
+ * see the top of this file), or gamma5 D(mass) in when flags has
+ * WD_FLAG_GAMMA5. in_dev and out_dev are packed spinors of precision prec
+ * (which must equal the precision of g) and must not overlap. mass = -4 gives
+ * the pure hopping term -H/2. Asynchronous on stream.
+ * Errors: WD_ERR_INVALID_ARG (NULL or overlapping buffers, precision mismatch,
+ * unknown flags), WD_ERR_DEVICE (launch). */
+WD_API int dslash_apply(const wd_gauge* g, double mass, const void* in_dev, void* out_dev,
+                 int32_t prec, int32_t flags, hipStream_t stream);
+
+#ifdef __cplusplus
+} /* extern "C" */
+#endif
+
+#endif /* WILSON_H */

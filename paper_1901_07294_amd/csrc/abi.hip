@@ -1,0 +1,262 @@
+// C entry points of wilson.h: argument checks, handles, dispatch to kernels.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "wd_internal.h"
+
+namespace wd {
+
+namespace {
+thread_local char g_last_error[512] = "";
+}
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void clear_error() { g_last_error[0] = '\0'; }
+
+size_t spinor_site_bytes(int prec) {
+  switch (prec) {
+    case WD_FP64: return 24 * sizeof(double);
+    case WD_FP32: return 24 * sizeof(float);
+    default: return 0;
+  }
+}
+
+size_t gauge_site_bytes(int prec, int c12) {
+  const size_t reals = 4 * (c12 ? 12 : 18);
+  switch (prec) {
+    case WD_FP64: return reals * sizeof(double);
+    case WD_FP32: return reals * sizeof(float);
+    default: return 0;
+  }
+}
+
+namespace {
+
+constexpr long kMaxSites = (1L << 31) / 12 - 1;  // keeps plane offsets in range
+
+// Validates dims; on success stores the volume in *V.
+int check_dims(const int32_t dims[4], long* V) {
+  if (dims == nullptr) return set_error(WD_ERR_INVALID_ARG, "dims is NULL");
+  long v = 1;
+  for (int i = 0; i < 4; ++i) {
+    if (dims[i] < 1)
+      return set_error(WD_ERR_SHAPE, "lattice extent %d is %d; every extent must be >= 1", i,
+                       dims[i]);
+    v *= dims[i];
+    if (v > kMaxSites) return set_error(WD_ERR_SHAPE, "lattice volume exceeds %ld sites", kMaxSites);
+  }
+  *V = v;
+  return WD_OK;
+}
+
+int check_prec(int prec) {
+  if (prec == WD_FP64 || prec == WD_FP32) return WD_OK;
+  if (prec == WD_FP16)
+    return set_error(WD_ERR_UNSUPPORTED, "precision WD_FP16 is not supported by this entry point");
+  return set_error(WD_ERR_INVALID_ARG, "unknown precision %d", prec);
+}
+
+// The range [p, p + bytes) must lie inside one device allocation on the
+// current device.
+int check_device_range(const void* p, size_t bytes, const char* what) {
+  if (p == nullptr) return set_error(WD_ERR_INVALID_ARG, "%s is NULL", what);
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(WD_ERR_INVALID_ARG, "%s (%p) is not a HIP device pointer", what, p);
+  }
+  if (attr.type != hipMemoryTypeDevice)
+    return set_error(WD_ERR_INVALID_ARG, "%s (%p) is not device memory (memory type %d)", what, p,
+                     static_cast<int>(attr.type));
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != attr.device)
+    return set_error(WD_ERR_INVALID_ARG, "%s lives on device %d, current device is %d", what,
+                     attr.device, dev);
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(WD_ERR_INVALID_ARG, "%s (%p): cannot query its allocation", what, p);
+  }
+  const char* b = static_cast<const char*>(base);
+  const char* q = static_cast<const char*>(p);
+  if (q < b || static_cast<size_t>(q - b) + bytes > size)
+    return set_error(WD_ERR_INVALID_ARG,
+                     "%s (%p) needs %zu bytes but its allocation ends %zu bytes after it", what, p,
+                     bytes, static_cast<size_t>(b + size - q));
+  return WD_OK;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + nb && y < x + na;
+}
+
+int check_gauge(const wd_gauge* g) {
+  if (g == nullptr) return set_error(WD_ERR_INVALID_ARG, "gauge handle is NULL");
+  if (g->magic != kGaugeMagic) return set_error(WD_ERR_INVALID_ARG, "not a live gauge handle");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != g->device)
+    return set_error(WD_ERR_INVALID_ARG, "gauge handle belongs to device %d, current device is %d",
+                     g->device, dev);
+  return WD_OK;
+}
+
+int launch_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return WD_OK;
+  return set_error(WD_ERR_DEVICE, "%s: launch failed: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+}  // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+int wd_abi_version(void) { return WD_ABI_VERSION; }
+
+const char* wd_last_error(void) { return g_last_error; }
+
+size_t wd_spinor_bytes(const int32_t dims[4], int32_t prec, int32_t nrhs) {
+  long V = 0;
+  if (check_dims(dims, &V) != WD_OK || nrhs < 0) return 0;
+  return static_cast<size_t>(V) * static_cast<size_t>(nrhs) * spinor_site_bytes(prec);
+}
+
+size_t wd_gauge_bytes(const int32_t dims[4], int32_t prec, int32_t compress12) {
+  long V = 0;
+  if (check_dims(dims, &V) != WD_OK) return 0;
+  return static_cast<size_t>(V) * gauge_site_bytes(prec, compress12 ? 1 : 0);
+}
+
+int wd_gauge_import(const int32_t dims[4], const void* U_canon_dev, int32_t prec,
+                    int32_t compress12, void* dst_dev, size_t dst_bytes, hipStream_t stream,
+                    wd_gauge** out) {
+  try {
+    clear_error();
+    if (out == nullptr) return set_error(WD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    long V = 0;
+    int rc = check_dims(dims, &V);
+    if (rc != WD_OK) return rc;
+    if ((rc = check_prec(prec)) != WD_OK) return rc;
+    const int c12 = compress12 ? 1 : 0;
+    const size_t need = static_cast<size_t>(V) * gauge_site_bytes(prec, c12);
+    if (dst_bytes < need)
+      return set_error(WD_ERR_INVALID_ARG, "dst_bytes %zu < %zu needed", dst_bytes, need);
+    const size_t canon_bytes = static_cast<size_t>(V) * 36 * 16;
+    if ((rc = check_device_range(U_canon_dev, canon_bytes, "U_canon_dev")) != WD_OK) return rc;
+    if ((rc = check_device_range(dst_dev, need, "dst_dev")) != WD_OK) return rc;
+    if (overlaps(U_canon_dev, canon_bytes, dst_dev, need))
+      return set_error(WD_ERR_INVALID_ARG, "U_canon_dev and dst_dev overlap");
+    wd_gauge* g = new (std::nothrow) wd_gauge;
+    if (g == nullptr) return set_error(WD_ERR_NOMEM, "host allocation of the handle failed");
+    g->magic = kGaugeMagic;
+    for (int i = 0; i < 4; ++i) g->dims[i] = dims[i];
+    g->V = V;
+    g->prec = prec;
+    g->c12 = c12;
+    (void)hipGetDevice(&g->device);
+    g->links = dst_dev;
+    g->link_bytes = need;
+    rc = launch_status(launch_pack_gauge(U_canon_dev, dst_dev, make_geo(dims), prec, c12, stream),
+                       "pack_gauge");
+    if (rc != WD_OK) {
+      g->magic = 0;
+      delete g;
+      return rc;
+    }
+    *out = g;
+    return WD_OK;
+  } catch (...) {
+    return set_error(WD_ERR_INTERNAL, "unexpected exception in wd_gauge_import");
+  }
+}
+
+int wd_gauge_release(wd_gauge* g) {
+  clear_error();
+  if (g == nullptr) return WD_OK;
+  if (g->magic != kGaugeMagic) return set_error(WD_ERR_INVALID_ARG, "not a live gauge handle");
+  g->magic = 0;
+  delete g;
+  return WD_OK;
+}
+
+static int spinor_transfer(const wd_gauge* g, const void* src, int32_t prec, int32_t nrhs, void* dst,
+                           hipStream_t stream, bool import) {
+  int rc = check_gauge(g);
+  if (rc != WD_OK) return rc;
+  if ((rc = check_prec(prec)) != WD_OK) return rc;
+  if (prec != g->prec)
+    return set_error(WD_ERR_INVALID_ARG, "spinor precision %d differs from the gauge field's %d",
+                     prec, g->prec);
+  if (nrhs < 0) return set_error(WD_ERR_INVALID_ARG, "nrhs is %d", nrhs);
+  if (nrhs == 0) return WD_OK;
+  const size_t canon = static_cast<size_t>(g->V) * nrhs * 12 * 16;
+  const size_t packed = static_cast<size_t>(g->V) * nrhs * spinor_site_bytes(prec);
+  const size_t nsrc = import ? canon : packed;
+  const size_t ndst = import ? packed : canon;
+  if ((rc = check_device_range(src, nsrc, import ? "canon_dev" : "src_dev")) != WD_OK) return rc;
+  if ((rc = check_device_range(dst, ndst, import ? "dst_dev" : "canon_dev")) != WD_OK) return rc;
+  if (overlaps(src, nsrc, dst, ndst)) return set_error(WD_ERR_INVALID_ARG, "buffers overlap");
+  const Geo geo = make_geo(g->dims);
+  return launch_status(import ? launch_pack_spinor(src, dst, geo, prec, nrhs, stream)
+                              : launch_unpack_spinor(src, dst, geo, prec, nrhs, stream),
+                       import ? "pack_spinor" : "unpack_spinor");
+}
+
+int wd_spinor_import(const wd_gauge* g, const void* canon_dev, int32_t prec, int32_t nrhs,
+                     void* dst_dev, hipStream_t stream) {
+  try {
+    clear_error();
+    return spinor_transfer(g, canon_dev, prec, nrhs, dst_dev, stream, true);
+  } catch (...) {
+    return set_error(WD_ERR_INTERNAL, "unexpected exception in wd_spinor_import");
+  }
+}
+
+int wd_spinor_export(const wd_gauge* g, const void* src_dev, int32_t prec, int32_t nrhs,
+                     void* canon_dev, hipStream_t stream) {
+  try {
+    clear_error();
+    return spinor_transfer(g, src_dev, prec, nrhs, canon_dev, stream, false);
+  } catch (...) {
+    return set_error(WD_ERR_INTERNAL, "unexpected exception in wd_spinor_export");
+  }
+}
+
+int dslash_apply(const wd_gauge* g, double mass, const void* in_dev, void* out_dev, int32_t prec,
+                 int32_t flags, hipStream_t stream) {
+  try {
+    clear_error();
+    int rc = check_gauge(g);
+    if (rc != WD_OK) return rc;
+    if ((rc = check_prec(prec)) != WD_OK) return rc;
+    if (prec != g->prec)
+      return set_error(WD_ERR_INVALID_ARG, "spinor precision %d differs from the gauge field's %d",
+                       prec, g->prec);
+    if (flags & ~WD_FLAG_GAMMA5) return set_error(WD_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const size_t n = static_cast<size_t>(g->V) * spinor_site_bytes(prec);
+    if ((rc = check_device_range(in_dev, n, "in_dev")) != WD_OK) return rc;
+    if ((rc = check_device_range(out_dev, n, "out_dev")) != WD_OK) return rc;
+    if (overlaps(in_dev, n, out_dev, n)) return set_error(WD_ERR_INVALID_ARG, "in_dev and out_dev overlap");
+    return launch_status(launch_dslash(g, mass, in_dev, out_dev, flags, stream), "dslash");
+  } catch (...) {
+    return set_error(WD_ERR_INTERNAL, "unexpected exception in dslash_apply");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// Packed device layouts of spinor and gauge fields, and their loads/stores.
+//
+// Every packed field is a structure of arrays with the site index fastest, so
+// that the 64 lanes of a wave, which hold 64 consecutive sites, read and write
+// contiguous 512 B - 1 KiB runs (Sec. II-B: the data layout decides how well
+// the stencil vectorises; here one lane per site plays the role of Grid's
+// one vector lane per virtual node, without any intra-vector permutes).
+//
+//  spinor, per right-hand side k (stride 24*V reals):
+//    FP64: 12 planes of V double2   plane c = 3*spin + colour
+//    FP32:  6 planes of V float4    plane j holds components 2j, 2j+1
+//  gauge, direction mu:
+//    FP64 full: 9 planes of V double2 per mu   plane 9*mu + 3*row + col
+//    FP64 c12 : 6 planes of V double2 per mu   rows 0 and 1 only
+//    FP32 full: 9 planes of V float2 per mu
+//    FP32 c12 : 3 planes of V float4 per mu    plane j holds entries 2j, 2j+1 of rows 0-1
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cplx.h"
+
+namespace wd {
+
+// Vector types of packed spinors (S) and links (L) per arithmetic precision.
+template <typename R>
+struct Packed;
+template <>
+struct Packed<double> {
+  using S = double2;
+  using L = double2;
+};
+template <>
+struct Packed<float> {
+  using S = float4;
+  using L = float2;
+};
+
+// Native vector types for the non-temporal (streaming) stores of results.
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ spinors
+
+__device__ __forceinline__ void load_spinor(const double2* __restrict__ p, long V, int s,
+                                            cx<double> (&v)[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const double2 t = p[c * V + s];
+    v[c] = {t.x, t.y};
+  }
+}
+
+__device__ __forceinline__ void load_spinor(const float4* __restrict__ p, long V, int s,
+                                            cx<float> (&v)[12]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const float4 t = p[j * V + s];
+    v[2 * j] = {t.x, t.y};
+    v[2 * j + 1] = {t.z, t.w};
+  }
+}
+
+__device__ __forceinline__ void store_spinor(double2* __restrict__ p, long V, int s,
+                                             const cx<double> (&v)[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const nd2 t = {v[c].re, v[c].im};
+    __builtin_nontemporal_store(t, reinterpret_cast<nd2*>(p + c * V + s));
+  }
+}
+
+__device__ __forceinline__ void store_spinor(float4* __restrict__ p, long V, int s,
+                                             const cx<float> (&v)[12]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const nf4 t = {v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im};
+    __builtin_nontemporal_store(t, reinterpret_cast<nf4*>(p + j * V + s));
+  }
+}
+
+// -------------------------------------------------------------------- links
+
+// Third row of an SU(3) matrix from its first two: r2 = conj(r0 x r1).
+template <typename R>
+__device__ __forceinline__ void rebuild_row2(cx<R> (&u)[9]) {
+  u[6] = conj(mul(u[1], u[5]) - mul(u[2], u[4]));
+  u[7] = conj(mul(u[2], u[3]) - mul(u[0], u[5]));
+  u[8] = conj(mul(u[0], u[4]) - mul(u[1], u[3]));
+}
+
+template <bool C12>
+__device__ __forceinline__ void load_link(const double2* __restrict__ p, long V, int mu, int s,
+                                          cx<double> (&u)[9]) {
+  constexpr int n = C12 ? 6 : 9;
+#pragma unroll
+  for (int k = 0; k < n; ++k) {
+    const double2 t = p[(mu * n + k) * V + s];
+    u[k] = {t.x, t.y};
+  }
+  if constexpr (C12) rebuild_row2(u);
+}
+
+template <bool C12>
+__device__ __forceinline__ void load_link(const float2* __restrict__ p, long V, int mu, int s,
+                                          cx<float> (&u)[9]) {
+  if constexpr (C12) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const float4 t = q[(mu * 3 + j) * V + s];
+      u[2 * j] = {t.x, t.y};
+      u[2 * j + 1] = {t.z, t.w};
+    }
+    rebuild_row2(u);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const float2 t = p[(mu * 9 + k) * V + s];
+      u[k] = {t.x, t.y};
+    }
+  }
+}
+
+}  // namespace wd

@@ -1,0 +1,63 @@
+// Internal declarations of the Wilson-Dirac library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "wilson.h"
+
+// The handle behind wd_gauge*: geometry plus the caller-owned packed links.
+struct wd_gauge {
+  uint64_t magic;
+  int32_t dims[4];   // X, Y, Z, T
+  int64_t V;         // number of sites
+  int32_t prec;      // wd_prec of the packed links and of the spinors used with them
+  int32_t c12;       // links stored as two rows (12 reals)
+  int device;        // HIP device the packed links live on
+  void* links;       // packed links (caller-owned)
+  size_t link_bytes;
+};
+
+namespace wd {
+
+constexpr uint64_t kGaugeMagic = 0x57444741554745ull;  // "WDGAUGE"
+constexpr int kBlock = 256;                           // threads per workgroup, 4 wave64s
+constexpr int kNumXcd = 8;                            // MI355X: 8 XCDs, 32 CUs each
+
+// Set the thread's last-error text; returns code for `return set_error(...)`.
+int set_error(int code, const char* fmt, ...);
+void clear_error();
+
+// Geometry passed to kernels by value.
+struct Geo {
+  int X, Y, Z, T;
+  int XY, XYZ;
+  int V;
+};
+
+inline Geo make_geo(const int32_t d[4]) {
+  Geo g;
+  g.X = d[0]; g.Y = d[1]; g.Z = d[2]; g.T = d[3];
+  g.XY = g.X * g.Y;
+  g.XYZ = g.XY * g.Z;
+  g.V = g.XYZ * g.T;
+  return g;
+}
+
+// Bytes per site of packed fields.
+size_t spinor_site_bytes(int prec);
+size_t gauge_site_bytes(int prec, int c12);
+
+// Kernel launchers (enqueue only; return the launch status).
+hipError_t launch_pack_gauge(const void* canon, void* dst, const Geo& geo, int prec, int c12,
+                             hipStream_t s);
+hipError_t launch_pack_spinor(const void* canon, void* dst, const Geo& geo, int prec, int nrhs,
+                              hipStream_t s);
+hipError_t launch_unpack_spinor(const void* src, void* canon, const Geo& geo, int prec, int nrhs,
+                                hipStream_t s);
+hipError_t launch_dslash(const wd_gauge* g, double mass, const void* in, void* out, int flags,
+                         hipStream_t s);
+
+}  // namespace wd

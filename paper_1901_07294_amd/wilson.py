@@ -1,0 +1,202 @@
+"""Python binding of the C ABI in include/wilson.h (argument marshalling only).
+
+Every function has the name of its C entry point and forwards to it through
+ctypes; all arithmetic runs in the HIP library. Device buffers may be given as
+torch tensors (their ``data_ptr()`` is passed) or as integer addresses.
+``stream=None`` means torch's current stream on the current device.
+
+The library must have been built (``python -m paper_1901_07294_amd.build``);
+the first call raises ImportError if ``libwilson.so`` is missing. There is no
+fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwilson.so")
+
+WD_OK = 0
+WD_PENDING = 1
+WD_ERR_INVALID_ARG = -1
+WD_ERR_SHAPE = -2
+WD_ERR_UNSUPPORTED = -3
+WD_ERR_NOMEM = -4
+WD_ERR_DEVICE = -5
+WD_ERR_NOT_CONVERGED = -6
+WD_ERR_NUMERIC = -7
+WD_ERR_UNKNOWN_TICKET = -8
+WD_ERR_CANCELLED = -9
+WD_ERR_INTERNAL = -10
+
+WD_FP64 = 0
+WD_FP32 = 1
+WD_FP16 = 2
+
+WD_FLAG_GAMMA5 = 1
+
+STATUS_NAMES = {v: k for k, v in dict(globals()).items()
+                if k.startswith("WD_ERR_") or k in ("WD_OK", "WD_PENDING")}
+
+# Exported C symbols and their ctypes signatures.
+_i32 = ctypes.c_int32
+_vp = ctypes.c_void_p
+_dims_t = ctypes.POINTER(ctypes.c_int32)
+SIGNATURES = {
+    "wd_abi_version": (ctypes.c_int, []),
+    "wd_last_error": (ctypes.c_char_p, []),
+    "wd_spinor_bytes": (ctypes.c_size_t, [_dims_t, _i32, _i32]),
+    "wd_gauge_bytes": (ctypes.c_size_t, [_dims_t, _i32, _i32]),
+    "wd_gauge_import": (ctypes.c_int, [_dims_t, _vp, _i32, _i32, _vp, ctypes.c_size_t, _vp,
+                                       ctypes.POINTER(_vp)]),
+    "wd_gauge_release": (ctypes.c_int, [_vp]),
+    "wd_spinor_import": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp]),
+    "wd_spinor_export": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp]),
+    "dslash_apply": (ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp, _i32, _i32, _vp]),
+}
+
+
+class WilsonError(RuntimeError):
+    """A negative status returned by the library."""
+
+    def __init__(self, func: str, code: int, message: str):
+        self.code = code
+        super().__init__(f"{func}: {STATUS_NAMES.get(code, code)}: {message}")
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is not built; run `python -m paper_1901_07294_amd.build` first")
+    lib = ctypes.CDLL(_LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = None
+LIB_PATH = _LIB_PATH
+
+
+def _L():
+    """The loaded library (loaded on first use)."""
+    global _lib
+    if _lib is None:
+        _lib = _load()
+    return _lib
+
+
+def _dims(dims):
+    d = [int(v) for v in dims]
+    if len(d) != 4:
+        raise ValueError("dims must have 4 entries (X, Y, Z, T)")
+    return (ctypes.c_int32 * 4)(*d)
+
+
+def _ptr(buf):
+    if buf is None:
+        return None
+    if hasattr(buf, "data_ptr"):
+        return buf.data_ptr()
+    return int(buf)
+
+
+def _nbytes(buf):
+    if hasattr(buf, "untyped_storage"):
+        return buf.numel() * buf.element_size()
+    raise TypeError("pass dst_bytes explicitly for a raw address")
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _check(func, rc):
+    if rc < 0:
+        raise WilsonError(func, rc, _L().wd_last_error().decode())
+    return rc
+
+
+def wd_abi_version() -> int:
+    return _L().wd_abi_version()
+
+
+def wd_last_error() -> str:
+    return _L().wd_last_error().decode()
+
+
+def wd_spinor_bytes(dims, prec, nrhs=1) -> int:
+    return _L().wd_spinor_bytes(_dims(dims), prec, nrhs)
+
+
+def wd_gauge_bytes(dims, prec, compress12=0) -> int:
+    return _L().wd_gauge_bytes(_dims(dims), prec, int(bool(compress12)))
+
+
+class Gauge:
+    """Owns a wd_gauge* handle (released on close/GC) and keeps its buffer alive."""
+
+    def __init__(self, handle, dims, prec, compress12, buf):
+        self.handle = handle
+        self.dims = tuple(int(v) for v in dims)
+        self.prec = prec
+        self.compress12 = bool(compress12)
+        self._buf = buf
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+    def close(self):
+        if self.handle:
+            _check("wd_gauge_release", _L().wd_gauge_release(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def wd_gauge_import(dims, U_canon, prec, compress12, dst, dst_bytes=None, stream=None) -> Gauge:
+    out = ctypes.c_void_p()
+    nb = _nbytes(dst) if dst_bytes is None else int(dst_bytes)
+    _check("wd_gauge_import", _L().wd_gauge_import(
+        _dims(dims), _ptr(U_canon), prec, int(bool(compress12)), _ptr(dst), nb,
+        _stream(stream), ctypes.byref(out)))
+    return Gauge(out.value, dims, prec, compress12, dst)
+
+
+def wd_gauge_release(g) -> int:
+    if isinstance(g, Gauge):
+        g.close()
+        return WD_OK
+    return _check("wd_gauge_release", _L().wd_gauge_release(g))
+
+
+def _h(g):
+    return g.handle if isinstance(g, Gauge) else g
+
+
+def wd_spinor_import(g, canon, prec, nrhs, dst, stream=None) -> int:
+    return _check("wd_spinor_import", _L().wd_spinor_import(
+        _h(g), _ptr(canon), prec, nrhs, _ptr(dst), _stream(stream)))
+
+
+def wd_spinor_export(g, src, prec, nrhs, canon, stream=None) -> int:
+    return _check("wd_spinor_export", _L().wd_spinor_export(
+        _h(g), _ptr(src), prec, nrhs, _ptr(canon), _stream(stream)))
+
+
+def dslash_apply(g, mass, inp, out, prec, flags=0, stream=None) -> int:
+    return _check("dslash_apply", _L().dslash_apply(
+        _h(g), float(mass), _ptr(inp), _ptr(out), prec, flags, _stream(stream)))
