@@ -9,102 +9,60 @@
 // The stencil is bound by HBM bandwidth (1320 flop against >= 960 compulsory
 // bytes per site in FP64), so there is no matrix-core work here: every lane
 // streams its site's links and spinor planes, coalesced across the wave.
-// Each hop first projects the 4-spinor to a 2-spinor, h = psi_u -/+ A_mu psi_l
-// with gamma_mu = [[0, A_mu], [A_mu^dag, 0]] in the DeGrand-Rossi basis, then
-// multiplies by the SU(3) link (2 colour matrix-vector products instead of 4)
-// and rebuilds the lower spin components as -/+ A_mu^dag (U h).
-#include "fields.h"
+#include <atomic>
+
+#include "stencil.h"
 #include "wd_internal.h"
+
+// Compile-time tuning knobs (the defaults are the measured best on MI355X).
+#ifndef WD_DSLASH_BLOCK
+#define WD_DSLASH_BLOCK 256   // threads per workgroup
+#endif
+#ifndef WD_XCD_GROUP
+#define WD_XCD_GROUP -1       // tiles per XCD run; -1 picks automatically
+#endif
+#ifndef WD_DSLASH_KERNEL
+#define WD_DSLASH_KERNEL 2    // 2: t-marching, 0: split t-marching, 1: one site per lane
+#endif
+#ifndef WD_MARCH_THREADS
+#define WD_MARCH_THREADS 256  // target sites per t-marching tile
+#endif
+#ifndef WD_MARCH_BLOCKS
+#define WD_MARCH_BLOCKS 512   // target t-marching workgroups per launch
+#endif
+#ifndef WD_MARCH_XCD_GROUP
+#define WD_MARCH_XCD_GROUP 32 // preferred XCD run length of t-marching tiles
+#endif
+#ifndef WD_MARCH_EARLY_OUTER
+#define WD_MARCH_EARLY_OUTER 1 // z / off-tile y hops of t+1 at the start (1) or end (0) of step t
+#endif
+#ifndef WD_MARCH_WAVES
+#define WD_MARCH_WAVES 0      // occupancy hint for the t-marching kernel; 0 = none
+#endif
+#ifndef WD_WAVES_PER_EU
+#define WD_WAVES_PER_EU 0     // occupancy hint to the register allocator; 0 = none
+#endif
+
+#if WD_WAVES_PER_EU > 0
+#define WD_OCCUPANCY __attribute__((amdgpu_waves_per_eu(WD_WAVES_PER_EU)))
+#else
+#define WD_OCCUPANCY
+#endif
+#if WD_MARCH_WAVES > 0
+#define WD_MARCH_OCCUPANCY __attribute__((amdgpu_waves_per_eu(WD_MARCH_WAVES)))
+#else
+#define WD_MARCH_OCCUPANCY
+#endif
 
 namespace wd {
 namespace {
 
-// h = psi_u + S * A_mu psi_l (S = -1 forward hop, +1 backward hop). psi is
-// indexed 3*spin + colour; h is indexed 3*halfspin + colour.
-//   A_x = [[0, i], [i, 0]]   A_y = [[0, -1], [1, 0]]
-//   A_z = [[i, 0], [0, -i]]  A_t = [[1, 0], [0, 1]]
-template <int MU, int S, typename R>
-__device__ __forceinline__ void project(const cx<R> (&p)[12], cx<R> (&h)[6]) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const cx<R> p0 = p[a], p1 = p[3 + a], p2 = p[6 + a], p3 = p[9 + a];
-    if constexpr (MU == 0) {
-      h[a] = S > 0 ? addi(p0, p3) : subi(p0, p3);
-      h[3 + a] = S > 0 ? addi(p1, p2) : subi(p1, p2);
-    } else if constexpr (MU == 1) {
-      h[a] = S > 0 ? p0 - p3 : p0 + p3;
-      h[3 + a] = S > 0 ? p1 + p2 : p1 - p2;
-    } else if constexpr (MU == 2) {
-      h[a] = S > 0 ? addi(p0, p2) : subi(p0, p2);
-      h[3 + a] = S > 0 ? subi(p1, p3) : addi(p1, p3);
-    } else {
-      h[a] = S > 0 ? p0 + p2 : p0 - p2;
-      h[3 + a] = S > 0 ? p1 + p3 : p1 - p3;
-    }
-  }
-}
-
-// acc += (U h, S * A_mu^dag (U h)); g = U h (or U^dag h) indexed like h.
-//   A_x^dag = [[0, -i], [-i, 0]]   A_y^dag = [[0, 1], [-1, 0]]
-//   A_z^dag = [[-i, 0], [0, i]]    A_t^dag = 1
-template <int MU, int S, typename R>
-__device__ __forceinline__ void reconstruct_add(const cx<R> (&g)[6], cx<R> (&acc)[12]) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const cx<R> g0 = g[a], g1 = g[3 + a];
-    acc[a] = acc[a] + g0;
-    acc[3 + a] = acc[3 + a] + g1;
-    if constexpr (MU == 0) {  // lower = S * (-i g1, -i g0)
-      acc[6 + a] = S > 0 ? subi(acc[6 + a], g1) : addi(acc[6 + a], g1);
-      acc[9 + a] = S > 0 ? subi(acc[9 + a], g0) : addi(acc[9 + a], g0);
-    } else if constexpr (MU == 1) {  // lower = S * (g1, -g0)
-      acc[6 + a] = S > 0 ? acc[6 + a] + g1 : acc[6 + a] - g1;
-      acc[9 + a] = S > 0 ? acc[9 + a] - g0 : acc[9 + a] + g0;
-    } else if constexpr (MU == 2) {  // lower = S * (-i g0, i g1)
-      acc[6 + a] = S > 0 ? subi(acc[6 + a], g0) : addi(acc[6 + a], g0);
-      acc[9 + a] = S > 0 ? addi(acc[9 + a], g1) : subi(acc[9 + a], g1);
-    } else {  // lower = S * (g0, g1)
-      acc[6 + a] = S > 0 ? acc[6 + a] + g0 : acc[6 + a] - g0;
-      acc[9 + a] = S > 0 ? acc[9 + a] + g1 : acc[9 + a] - g1;
-    }
-  }
-}
-
-// g = U h (DAG = false) or U^dag h (DAG = true), on both colour vectors of h.
-template <bool DAG, typename R>
-__device__ __forceinline__ void su3_mul(const cx<R> (&u)[9], const cx<R> (&h)[6], cx<R> (&g)[6]) {
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if constexpr (!DAG) {
-        cx<R> r = mul(u[3 * a], h[3 * s]);
-        r = fma(u[3 * a + 1], h[3 * s + 1], r);
-        g[3 * s + a] = fma(u[3 * a + 2], h[3 * s + 2], r);
-      } else {
-        cx<R> r = cmul(u[a], h[3 * s]);
-        r = cfma(u[3 + a], h[3 * s + 1], r);
-        g[3 * s + a] = cfma(u[6 + a], h[3 * s + 2], r);
-      }
-    }
-  }
-}
-
-// One hop: neighbour spinor at site n, link of direction MU at site ls.
-template <int MU, int S, bool C12, typename R>
-__device__ __forceinline__ void hop(const typename Packed<R>::S* __restrict__ in,
-                                    const typename Packed<R>::L* __restrict__ links, long V, int n,
-                                    int ls, cx<R> (&acc)[12]) {
-  cx<R> psi[12];
-  load_spinor(in, V, n, psi);
-  cx<R> u[9];
-  load_link<C12>(links, V, MU, ls, u);
-  cx<R> h[6];
-  project<MU, S>(psi, h);
-  cx<R> g[6];
-  su3_mul<(S > 0)>(u, h, g);
-  reconstruct_add<MU, S>(g, acc);
-}
+constexpr int kDslashBlock = WD_DSLASH_BLOCK;
+constexpr int kMarchMaxThreads = 256;
+constexpr int kMarchTargetThreads = WD_MARCH_THREADS;
+constexpr int kMarchTargetBlocks = WD_MARCH_BLOCKS;
+constexpr int kMarchXcdGroup = WD_MARCH_XCD_GROUP;
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 
 // Workgroup -> tile of kBlock consecutive sites. Consecutive workgroups are
 // dispatched round-robin over the 8 XCDs, each with its own L2; with
@@ -120,11 +78,11 @@ __device__ __forceinline__ int tile_of_block(int group) {
 }
 
 template <typename R, bool C12>
-__global__ __launch_bounds__(kBlock) void dslash_kernel(const typename Packed<R>::S* __restrict__ in,
+__global__ __launch_bounds__(kDslashBlock) WD_OCCUPANCY void dslash_kernel(const typename Packed<R>::S* __restrict__ in,
                                                         typename Packed<R>::S* __restrict__ out,
                                                         const typename Packed<R>::L* __restrict__ links,
                                                         Geo geo, R diag, int gamma5, int group) {
-  const int s = tile_of_block(group) * kBlock + static_cast<int>(threadIdx.x);
+  const int s = tile_of_block(group) * kDslashBlock + static_cast<int>(threadIdx.x);
   if (s >= geo.V) return;
   const long V = geo.V;
 
@@ -157,19 +115,391 @@ __global__ __launch_bounds__(kBlock) void dslash_kernel(const typename Packed<R>
 
   cx<R> psi[12];
   load_spinor(in, V, s, psi);
-  const R half = R(0.5);
-#pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    cx<R> r = {diag * psi[c].re - half * acc[c].re, diag * psi[c].im - half * acc[c].im};
-    if (gamma5 && c >= 6) r = -r;
-    psi[c] = r;
-  }
-  store_spinor(out, V, s, psi);
+  cx<R> o[12];
+  epilogue(psi, acc, diag, gamma5, o);
+  store_spinor(out, V, s, o);
 }
 
-int default_xcd_group(int nblocks) {
-  // runs of 4 tiles (1024 sites) per XCD, when the grid allows it
-  return nblocks % (kNumXcd * 4) == 0 ? 4 : 0;
+// ---------------------------------------------------------------------------
+// t-marching kernel.
+//
+// A workgroup owns a tile of X x NY sites (whole x rows) at one z and walks
+// t0 .. t1-1. The tile's spinors at the current t sit in LDS (double
+// buffered), so the x and in-tile y neighbours are read from LDS; the t
+// neighbours come from the march itself: psi(t+1) is the workgroup's own
+// next slice, and the backward t hop of step t+1, U_t(t)^dag P+ psi(t), is
+// built from data of step t and carried in the accumulator. The z hops and
+// the y hops that leave the tile need other workgroups' sites; they are done
+// one step early, while the workgroups that own those sites load the same
+// slice, so their lines are still in L2.
+// ---------------------------------------------------------------------------
+
+struct MarchParams {
+  int ny;      // rows per tile (divides Y)
+  int tb;      // t steps per workgroup
+  int ytiles;  // Y / ny
+  int group;   // XCD run length (tiles), 0 = hardware order
+};
+
+// Hops of time t that involve sites outside the tile: z forward and
+// backward, and the y hops of the tile's edge rows.
+template <bool C12, typename R>
+__device__ __forceinline__ void outer_hops(const typename Packed<R>::S* __restrict__ in,
+                                           const typename Packed<R>::L* __restrict__ links, long V,
+                                           int st, int dzp, int dzm, bool y_fwd_out, int dyp,
+                                           bool y_bwd_out, int dym, cx<R> (&acc)[12]) {
+  hop<2, -1, C12, R>(in, links, V, st + dzp, st, acc);
+  hop<2, +1, C12, R>(in, links, V, st + dzm, st + dzm, acc);
+  if (y_fwd_out) hop<1, -1, C12, R>(in, links, V, st + dyp, st, acc);
+  if (y_bwd_out) hop<1, +1, C12, R>(in, links, V, st + dym, st + dym, acc);
+}
+
+template <typename R, bool C12>
+__global__ __launch_bounds__(kMarchMaxThreads) WD_MARCH_OCCUPANCY void dslash_march_kernel(
+    const typename Packed<R>::S* __restrict__ in, typename Packed<R>::S* __restrict__ out,
+    const typename Packed<R>::L* __restrict__ links, Geo geo, R diag, int gamma5, MarchParams p) {
+  using SV = typename Packed<R>::S;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = geo.X * p.ny;  // sites per tile == threads per workgroup
+  SV* buf0 = reinterpret_cast<SV*>(smem);
+  SV* buf1 = buf0 + (sizeof(R) == 8 ? 12 : 6) * n;
+  const long V = geo.V;
+
+  const int tid = static_cast<int>(threadIdx.x);
+  const int xl = tid % geo.X;
+  const int yl = tid / geo.X;
+  const int b = tile_of_block(p.group);
+  const int yt = b % p.ytiles;
+  const int z = (b / p.ytiles) % geo.Z;
+  const int tblk = b / (p.ytiles * geo.Z);
+  const int y = yt * p.ny + yl;
+  const int t0 = tblk * p.tb;
+  const int t1 = min(t0 + p.tb, geo.T);
+
+  const int s0 = xl + geo.X * (y + geo.Y * z);  // the site at t = 0
+  // LDS slots of the in-tile x and y neighbours
+  const int lxp = yl * geo.X + (xl + 1 == geo.X ? 0 : xl + 1);
+  const int lxm = yl * geo.X + (xl == 0 ? geo.X - 1 : xl - 1);
+  const bool whole_y = p.ny == geo.Y;
+  const bool y_fwd_out = !whole_y && yl + 1 == p.ny;
+  const bool y_bwd_out = !whole_y && yl == 0;
+  const int lyp = (yl + 1 == p.ny ? 0 : yl + 1) * geo.X + xl;
+  const int lym = (yl == 0 ? p.ny - 1 : yl - 1) * geo.X + xl;
+  // site offsets of the periodic neighbours
+  const int dxm = xl == 0 ? geo.X - 1 : -1;
+  const int dyp = y + 1 == geo.Y ? -(geo.Y - 1) * geo.X : geo.X;
+  const int dym = y == 0 ? (geo.Y - 1) * geo.X : -geo.X;
+  const int dzp = z + 1 == geo.Z ? -(geo.Z - 1) * geo.XY : geo.XY;
+  const int dzm = z == 0 ? (geo.Z - 1) * geo.XY : -geo.XY;
+
+  cx<R> acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+
+  // prologue: the carried hops of t0 and the first slice in LDS
+  {
+    const int tm = t0 == 0 ? geo.T - 1 : t0 - 1;
+    hop<3, +1, C12, R>(in, links, V, s0 + tm * geo.XYZ, s0 + tm * geo.XYZ, acc);
+    const int st = s0 + t0 * geo.XYZ;
+    outer_hops<C12, R>(in, links, V, st, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, acc);
+    cx<R> psi[12];
+    load_spinor(in, V, st, psi);
+    lds_store_spinor(buf0, n, tid, psi);
+  }
+  __syncthreads();
+
+  for (int t = t0; t < t1; ++t) {
+    SV* cur = ((t - t0) & 1) ? buf1 : buf0;
+    SV* nxt = ((t - t0) & 1) ? buf0 : buf1;
+    const int st = s0 + t * geo.XYZ;
+    const int sn = t + 1 == geo.T ? s0 : st + geo.XYZ;  // the site at t+1
+    const bool more = t + 1 < t1;
+
+    // Slice t+1: this workgroup's own spinors (forward t hop, next LDS
+    // slice) and, in the same window, the z and off-tile y hops of t+1,
+    // whose spinors other workgroups are loading as their own slice now.
+    cx<R> ut[9];
+    load_link<C12>(links, V, 3, st, ut);
+    cx<R> nacc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) nacc[c] = {R(0), R(0)};
+    {
+      cx<R> psi[12];
+      load_spinor(in, V, sn, psi);
+      if (more) {
+        lds_store_spinor(nxt, n, tid, psi);
+        if constexpr (WD_MARCH_EARLY_OUTER)
+          outer_hops<C12, R>(in, links, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, nacc);
+      }
+      cx<R> h[6], g[6];
+      project<3, -1>(psi, h);
+      su3_mul<false>(ut, h, g);
+      reconstruct_add<3, -1>(g, acc);
+    }
+    // x hops and in-tile y hops from LDS
+    {
+      cx<R> psi[12];
+      lds_load_spinor(cur, n, lxp, psi);
+      hop_psi<0, -1, C12, R>(psi, links, V, st, acc);
+      lds_load_spinor(cur, n, lxm, psi);
+      hop_psi<0, +1, C12, R>(psi, links, V, st + dxm, acc);
+      if (!y_fwd_out) {
+        lds_load_spinor(cur, n, lyp, psi);
+        hop_psi<1, -1, C12, R>(psi, links, V, st, acc);
+      }
+      if (!y_bwd_out) {
+        lds_load_spinor(cur, n, lym, psi);
+        hop_psi<1, +1, C12, R>(psi, links, V, st + dym, acc);
+      }
+    }
+    // epilogue of t; the backward t hop of t+1 joins the next accumulator
+    {
+      cx<R> psi[12];
+      lds_load_spinor(cur, n, tid, psi);
+      cx<R> o[12];
+      epilogue(psi, acc, diag, gamma5, o);
+      store_spinor(out, V, st, o);
+      if (more) {
+        cx<R> h[6], g[6];
+        project<3, +1>(psi, h);
+        su3_mul<true>(ut, h, g);
+        reconstruct_add<3, +1>(g, nacc);
+      }
+    }
+    if constexpr (!WD_MARCH_EARLY_OUTER)
+      if (more) outer_hops<C12, R>(in, links, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, nacc);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = nacc[c];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Split t-marching kernel: the same march with two lanes per site. The first
+// n lanes ("current") finish time t: the carried partial sum of t from LDS,
+// the forward t hop with their own psi(t+1), the x and in-tile y hops from
+// LDS, the epilogue and the store. The other n lanes ("next") meanwhile build
+// the carried partial sum of t+1: the backward t hop U_t(t)^dag P+ psi(t),
+// the z hops and the off-tile y hops, and hand it over through LDS. Each lane
+// keeps one accumulator, so the two halves fit twice the waves per CU.
+// ---------------------------------------------------------------------------
+
+template <typename R, bool C12>
+__global__ __launch_bounds__(2 * kMarchMaxThreads) WD_MARCH_OCCUPANCY void dslash_march2_kernel(
+    const typename Packed<R>::S* __restrict__ in, typename Packed<R>::S* __restrict__ out,
+    const typename Packed<R>::L* __restrict__ links, Geo geo, R diag, int gamma5, MarchParams p) {
+  using SV = typename Packed<R>::S;
+  constexpr int kPlanes = sizeof(R) == 8 ? 12 : 6;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = geo.X * p.ny;  // sites per tile; the workgroup has 2n lanes
+  SV* buf0 = reinterpret_cast<SV*>(smem);
+  SV* buf1 = buf0 + kPlanes * n;
+  SV* carry = buf1 + kPlanes * n;  // partial sums handed from "next" to "current" lanes
+  const long V = geo.V;
+
+  const bool next_lane = static_cast<int>(threadIdx.x) >= n;
+  const int tid = next_lane ? static_cast<int>(threadIdx.x) - n : static_cast<int>(threadIdx.x);
+  const int xl = tid % geo.X;
+  const int yl = tid / geo.X;
+  const int b = tile_of_block(p.group);
+  const int yt = b % p.ytiles;
+  const int z = (b / p.ytiles) % geo.Z;
+  const int tblk = b / (p.ytiles * geo.Z);
+  const int y = yt * p.ny + yl;
+  const int t0 = tblk * p.tb;
+  const int t1 = min(t0 + p.tb, geo.T);
+
+  const int s0 = xl + geo.X * (y + geo.Y * z);  // the site at t = 0
+  const int lxp = yl * geo.X + (xl + 1 == geo.X ? 0 : xl + 1);
+  const int lxm = yl * geo.X + (xl == 0 ? geo.X - 1 : xl - 1);
+  const bool whole_y = p.ny == geo.Y;
+  const bool y_fwd_out = !whole_y && yl + 1 == p.ny;
+  const bool y_bwd_out = !whole_y && yl == 0;
+  const int lyp = (yl + 1 == p.ny ? 0 : yl + 1) * geo.X + xl;
+  const int lym = (yl == 0 ? p.ny - 1 : yl - 1) * geo.X + xl;
+  const int dxm = xl == 0 ? geo.X - 1 : -1;
+  const int dyp = y + 1 == geo.Y ? -(geo.Y - 1) * geo.X : geo.X;
+  const int dym = y == 0 ? (geo.Y - 1) * geo.X : -geo.X;
+  const int dzp = z + 1 == geo.Z ? -(geo.Z - 1) * geo.XY : geo.XY;
+  const int dzm = z == 0 ? (geo.Z - 1) * geo.XY : -geo.XY;
+
+  // prologue: first slice into LDS; carried partial sum of t0
+  if (!next_lane) {
+    cx<R> psi[12];
+    load_spinor(in, V, s0 + t0 * geo.XYZ, psi);
+    lds_store_spinor(buf0, n, tid, psi);
+  } else {
+    cx<R> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+    const int tm = t0 == 0 ? geo.T - 1 : t0 - 1;
+    hop<3, +1, C12, R>(in, links, V, s0 + tm * geo.XYZ, s0 + tm * geo.XYZ, acc);
+    outer_hops<C12, R>(in, links, V, s0 + t0 * geo.XYZ, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym,
+                       acc);
+    lds_store_spinor(carry, n, tid, acc);
+  }
+  __syncthreads();
+
+  for (int t = t0; t < t1; ++t) {
+    SV* cur = ((t - t0) & 1) ? buf1 : buf0;
+    SV* nxt = ((t - t0) & 1) ? buf0 : buf1;
+    const int st = s0 + t * geo.XYZ;
+    const int sn = t + 1 == geo.T ? s0 : st + geo.XYZ;  // the site at t+1
+    const bool more = t + 1 < t1;
+    cx<R> acc[12];
+    if (!next_lane) {
+      lds_load_spinor(carry, n, tid, acc);
+      {
+        cx<R> psi[12];
+        load_spinor(in, V, sn, psi);
+        if (more) lds_store_spinor(nxt, n, tid, psi);
+        hop_psi<3, -1, C12, R>(psi, links, V, st, acc);
+      }
+      {
+        cx<R> psi[12];
+        lds_load_spinor(cur, n, lxp, psi);
+        hop_psi<0, -1, C12, R>(psi, links, V, st, acc);
+        lds_load_spinor(cur, n, lxm, psi);
+        hop_psi<0, +1, C12, R>(psi, links, V, st + dxm, acc);
+        if (!y_fwd_out) {
+          lds_load_spinor(cur, n, lyp, psi);
+          hop_psi<1, -1, C12, R>(psi, links, V, st, acc);
+        }
+        if (!y_bwd_out) {
+          lds_load_spinor(cur, n, lym, psi);
+          hop_psi<1, +1, C12, R>(psi, links, V, st + dym, acc);
+        }
+      }
+      {
+        cx<R> psi[12];
+        lds_load_spinor(cur, n, tid, psi);
+        cx<R> o[12];
+        epilogue(psi, acc, diag, gamma5, o);
+        store_spinor(out, V, st, o);
+      }
+    } else if (more) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+      {
+        cx<R> psi[12];
+        lds_load_spinor(cur, n, tid, psi);
+        hop_psi<3, +1, C12, R>(psi, links, V, st, acc);
+      }
+      outer_hops<C12, R>(in, links, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, acc);
+    }
+    __syncthreads();  // the carried sum of t has been read
+    if (next_lane && more) lds_store_spinor(carry, n, tid, acc);
+    __syncthreads();  // slice t+1 and the carried sum of t+1 are in LDS
+  }
+}
+
+int xcd_group(int nblocks, int preferred) {
+  if (WD_XCD_GROUP >= 0) return WD_XCD_GROUP;
+  for (int g = preferred; g > 1; g /= 2)
+    if (nblocks % (kNumXcd * g) == 0) return g;
+  return 0;
+}
+
+// Geometry of the t-marching kernel for a lattice, or ny = 0 if it does not
+// apply (x rows longer than a workgroup, or too few sites per tile).
+size_t march_lds_bytes(int threads, size_t real_bytes) {
+  return 2 * 24 * real_bytes * static_cast<size_t>(threads);  // two spinor slices
+}
+
+size_t march2_lds_bytes(int sites, size_t real_bytes) {
+  return 3 * 24 * real_bytes * static_cast<size_t>(sites);  // two slices + carried sums
+}
+
+MarchParams march_params(const Geo& geo, size_t real_bytes) {
+  MarchParams p{0, 0, 0, 0};
+  if (geo.X > kMarchMaxThreads) return p;
+  int ny = 0;
+  for (int d = 1; d <= geo.Y; ++d)
+    if (geo.Y % d == 0 && geo.X * d <= kMarchTargetThreads &&
+        march2_lds_bytes(geo.X * d, real_bytes) <= kLdsBytes)
+      ny = d;
+  if (ny == 0 || geo.X * ny < 64) return p;
+  p.ny = ny;
+  p.ytiles = geo.Y / ny;
+  const int planes = p.ytiles * geo.Z;
+  // enough workgroups to fill every CU once; t steps split evenly
+  int nt = (kMarchTargetBlocks + planes - 1) / planes;
+  nt = nt < 1 ? 1 : (nt > geo.T ? geo.T : nt);
+  p.tb = (geo.T + nt - 1) / nt;
+  const int nb = planes * ((geo.T + p.tb - 1) / p.tb);
+  p.group = xcd_group(nb, kMarchXcdGroup);
+  return p;
+}
+
+template <typename R, bool C12>
+hipError_t launch_march(const void* in, void* out, const void* links, const Geo& geo, R diag,
+                        int g5, const MarchParams& p, hipStream_t st) {
+  using SV = typename Packed<R>::S;
+  using LV = typename Packed<R>::L;
+  const int threads = geo.X * p.ny;
+  const size_t lds = march_lds_bytes(threads, sizeof(R));
+  // raise the kernel's dynamic LDS limit once to the whole LDS of a CU
+  static std::atomic<int> attr_set{0};
+  if (!attr_set.load(std::memory_order_acquire)) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dslash_march_kernel<R, C12>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(kLdsBytes));
+    if (e != hipSuccess) return e;
+    attr_set.store(1, std::memory_order_release);
+  }
+  const unsigned nb = static_cast<unsigned>(p.ytiles * geo.Z * ((geo.T + p.tb - 1) / p.tb));
+  dslash_march_kernel<R, C12><<<nb, threads, lds, st>>>(
+      static_cast<const SV*>(in), static_cast<SV*>(out), static_cast<const LV*>(links), geo, diag,
+      g5, p);
+  return hipGetLastError();
+}
+
+template <typename R, bool C12>
+hipError_t launch_march2(const void* in, void* out, const void* links, const Geo& geo, R diag,
+                         int g5, const MarchParams& p, hipStream_t st) {
+  using SV = typename Packed<R>::S;
+  using LV = typename Packed<R>::L;
+  const int n = geo.X * p.ny;
+  const size_t lds = march2_lds_bytes(n, sizeof(R));
+  static std::atomic<int> attr_set{0};
+  if (!attr_set.load(std::memory_order_acquire)) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dslash_march2_kernel<R, C12>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(kLdsBytes));
+    if (e != hipSuccess) return e;
+    attr_set.store(1, std::memory_order_release);
+  }
+  const unsigned nb = static_cast<unsigned>(p.ytiles * geo.Z * ((geo.T + p.tb - 1) / p.tb));
+  dslash_march2_kernel<R, C12><<<nb, 2 * n, lds, st>>>(
+      static_cast<const SV*>(in), static_cast<SV*>(out), static_cast<const LV*>(links), geo, diag,
+      g5, p);
+  return hipGetLastError();
+}
+
+template <typename R, bool C12>
+hipError_t launch_site(const void* in, void* out, const void* links, const Geo& geo, R diag, int g5,
+                       hipStream_t st) {
+  using SV = typename Packed<R>::S;
+  using LV = typename Packed<R>::L;
+  const unsigned nb = static_cast<unsigned>((geo.V + kDslashBlock - 1) / kDslashBlock);
+  const int group = xcd_group(static_cast<int>(nb), 8);
+  dslash_kernel<R, C12><<<nb, kDslashBlock, 0, st>>>(static_cast<const SV*>(in),
+                                                       static_cast<SV*>(out),
+                                                       static_cast<const LV*>(links), geo, diag,
+                                                       g5, group);
+  return hipGetLastError();
+}
+
+template <typename R, bool C12>
+hipError_t launch_typed(const void* in, void* out, const void* links, const Geo& geo, double mass,
+                        int g5, hipStream_t st) {
+  const R diag = static_cast<R>(4.0 + mass);
+  const MarchParams p = march_params(geo, sizeof(R));
+  if (WD_DSLASH_KERNEL == 0 && p.ny > 0)
+    return launch_march2<R, C12>(in, out, links, geo, diag, g5, p, st);
+  if (WD_DSLASH_KERNEL == 2 && p.ny > 0)
+    return launch_march<R, C12>(in, out, links, geo, diag, g5, p, st);
+  return launch_site<R, C12>(in, out, links, geo, diag, g5, st);
 }
 
 }  // namespace
@@ -177,25 +507,12 @@ int default_xcd_group(int nblocks) {
 hipError_t launch_dslash(const wd_gauge* g, double mass, const void* in, void* out, int flags,
                          hipStream_t st) {
   const Geo geo = make_geo(g->dims);
-  const unsigned nb = static_cast<unsigned>((geo.V + kBlock - 1) / kBlock);
-  const int group = default_xcd_group(static_cast<int>(nb));
   const int g5 = (flags & WD_FLAG_GAMMA5) ? 1 : 0;
-  if (g->prec == WD_FP64) {
-    const auto* i = static_cast<const double2*>(in);
-    auto* o = static_cast<double2*>(out);
-    const auto* u = static_cast<const double2*>(g->links);
-    const double d = 4.0 + mass;
-    if (g->c12) dslash_kernel<double, true><<<nb, kBlock, 0, st>>>(i, o, u, geo, d, g5, group);
-    else dslash_kernel<double, false><<<nb, kBlock, 0, st>>>(i, o, u, geo, d, g5, group);
-  } else {
-    const auto* i = static_cast<const float4*>(in);
-    auto* o = static_cast<float4*>(out);
-    const auto* u = static_cast<const float2*>(g->links);
-    const float d = static_cast<float>(4.0 + mass);
-    if (g->c12) dslash_kernel<float, true><<<nb, kBlock, 0, st>>>(i, o, u, geo, d, g5, group);
-    else dslash_kernel<float, false><<<nb, kBlock, 0, st>>>(i, o, u, geo, d, g5, group);
-  }
-  return hipGetLastError();
+  if (g->prec == WD_FP64)
+    return g->c12 ? launch_typed<double, true>(in, out, g->links, geo, mass, g5, st)
+                  : launch_typed<double, false>(in, out, g->links, geo, mass, g5, st);
+  return g->c12 ? launch_typed<float, true>(in, out, g->links, geo, mass, g5, st)
+                : launch_typed<float, false>(in, out, g->links, geo, mass, g5, st);
 }
 
 }  // namespace wd

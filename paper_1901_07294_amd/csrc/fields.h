@@ -79,6 +79,35 @@ __device__ __forceinline__ void store_spinor(float4* __restrict__ p, long V, int
   }
 }
 
+// Spinors staged in LDS use the same plane layout over the n sites of a tile.
+__device__ __forceinline__ void lds_store_spinor(double2* p, int n, int i, const cx<double> (&v)[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) p[c * n + i] = make_double2(v[c].re, v[c].im);
+}
+
+__device__ __forceinline__ void lds_store_spinor(float4* p, int n, int i, const cx<float> (&v)[12]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+    p[j * n + i] = make_float4(v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im);
+}
+
+__device__ __forceinline__ void lds_load_spinor(const double2* p, int n, int i, cx<double> (&v)[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const double2 t = p[c * n + i];
+    v[c] = {t.x, t.y};
+  }
+}
+
+__device__ __forceinline__ void lds_load_spinor(const float4* p, int n, int i, cx<float> (&v)[12]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const float4 t = p[j * n + i];
+    v[2 * j] = {t.x, t.y};
+    v[2 * j + 1] = {t.z, t.w};
+  }
+}
+
 // -------------------------------------------------------------------- links
 
 // Third row of an SU(3) matrix from its first two: r2 = conj(r0 x r1).

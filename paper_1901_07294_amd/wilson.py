@@ -65,11 +65,11 @@ class WilsonError(RuntimeError):
         super().__init__(f"{func}: {STATUS_NAMES.get(code, code)}: {message}")
 
 
-def _load():
-    if not os.path.exists(_LIB_PATH):
+def _load(path=_LIB_PATH):
+    if not os.path.exists(path):
         raise ImportError(
-            f"{_LIB_PATH} is not built; run `python -m paper_1901_07294_amd.build` first")
-    lib = ctypes.CDLL(_LIB_PATH)
+            f"{path} is not built; run `python -m paper_1901_07294_amd.build` first")
+    lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
         fn.restype = res

@@ -27,6 +27,9 @@ SHAPES = [
     (1, 2, 3, 4),      # extent 1: the site is its own neighbour
     (16, 8, 8, 8),     # 8192 sites = 32 tiles: XCD-grouped tile order
     (12, 10, 6, 14),   # 10080 sites: many tiles + ragged tail
+    (32, 32, 16, 11),  # t-marching, 3 steps per workgroup, ragged last t block
+    (24, 24, 4, 8),    # t-marching, 24-wide rows (3 waves), 3 y tiles per plane
+    (64, 2, 2, 3),     # t-marching, extent-2 y and z
 ]
 
 
