@@ -37,9 +37,13 @@ def compulsory_bytes(prec: str, c12: bool) -> int:
 # HBM traffic of the dslash kernel measured with rocprofv3 --pmc (FETCH_SIZE,
 # WRITE_SIZE), scaled by the same counters on a plain copy of known size; valid
 # only for the kernel sources it was measured on (hash below), else null.
-TRAFFIC = {}
-KERNEL_SOURCES = ["paper_1901_07294_amd/csrc/dslash.hip", "paper_1901_07294_amd/csrc/fields.h",
-                  "paper_1901_07294_amd/csrc/cplx.h"]
+TRAFFIC = {
+    # FETCH_SIZE 880,922.6 KiB x 2.0 + WRITE_SIZE 393,273.7 KiB x 1.0 (copy-calibrated)
+    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "f389be291df978d3",
+                                       "bytes_per_launch": 2206841795},
+}
+KERNEL_SOURCES = ["paper_1901_07294_amd/csrc/dslash.hip", "paper_1901_07294_amd/csrc/stencil.h",
+                  "paper_1901_07294_amd/csrc/fields.h", "paper_1901_07294_amd/csrc/cplx.h"]
 
 
 def kernel_source_hash() -> str:
@@ -217,7 +221,7 @@ def main(argv=None):
                      "algorithmic_bytes_per_launch": cbytes * V},
         "parity": {"rel_err": parity, "tol": tol, "sites": int(len(sites)), "ok": parity <= tol},
         "pack_ms": round(pack_ms, 4),
-        "copy_ceiling_gbs": round(copy_gbs, 1),
+        "torch_copy_gbs": round(copy_gbs, 1),
         "variants": variants,
         "kernel_source_sha": kernel_source_hash(),
         "cpu_baseline": cpu,

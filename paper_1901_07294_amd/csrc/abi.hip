@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 
+#include "fields.h"
 #include "wd_internal.h"
 
 namespace wd {
@@ -133,13 +134,13 @@ const char* wd_last_error(void) { return g_last_error; }
 size_t wd_spinor_bytes(const int32_t dims[4], int32_t prec, int32_t nrhs) {
   long V = 0;
   if (check_dims(dims, &V) != WD_OK || nrhs < 0) return 0;
-  return static_cast<size_t>(V) * static_cast<size_t>(nrhs) * spinor_site_bytes(prec);
+  return static_cast<size_t>(packed_sites(V)) * static_cast<size_t>(nrhs) * spinor_site_bytes(prec);
 }
 
 size_t wd_gauge_bytes(const int32_t dims[4], int32_t prec, int32_t compress12) {
   long V = 0;
   if (check_dims(dims, &V) != WD_OK) return 0;
-  return static_cast<size_t>(V) * gauge_site_bytes(prec, compress12 ? 1 : 0);
+  return static_cast<size_t>(packed_sites(V)) * gauge_site_bytes(prec, compress12 ? 1 : 0);
 }
 
 int wd_gauge_import(const int32_t dims[4], const void* U_canon_dev, int32_t prec,
@@ -154,7 +155,7 @@ int wd_gauge_import(const int32_t dims[4], const void* U_canon_dev, int32_t prec
     if (rc != WD_OK) return rc;
     if ((rc = check_prec(prec)) != WD_OK) return rc;
     const int c12 = compress12 ? 1 : 0;
-    const size_t need = static_cast<size_t>(V) * gauge_site_bytes(prec, c12);
+    const size_t need = static_cast<size_t>(packed_sites(V)) * gauge_site_bytes(prec, c12);
     if (dst_bytes < need)
       return set_error(WD_ERR_INVALID_ARG, "dst_bytes %zu < %zu needed", dst_bytes, need);
     const size_t canon_bytes = static_cast<size_t>(V) * 36 * 16;
@@ -206,7 +207,7 @@ static int spinor_transfer(const wd_gauge* g, const void* src, int32_t prec, int
   if (nrhs < 0) return set_error(WD_ERR_INVALID_ARG, "nrhs is %d", nrhs);
   if (nrhs == 0) return WD_OK;
   const size_t canon = static_cast<size_t>(g->V) * nrhs * 12 * 16;
-  const size_t packed = static_cast<size_t>(g->V) * nrhs * spinor_site_bytes(prec);
+  const size_t packed = static_cast<size_t>(packed_sites(g->V)) * nrhs * spinor_site_bytes(prec);
   const size_t nsrc = import ? canon : packed;
   const size_t ndst = import ? packed : canon;
   if ((rc = check_device_range(src, nsrc, import ? "canon_dev" : "src_dev")) != WD_OK) return rc;
@@ -249,7 +250,7 @@ int dslash_apply(const wd_gauge* g, double mass, const void* in_dev, void* out_d
       return set_error(WD_ERR_INVALID_ARG, "spinor precision %d differs from the gauge field's %d",
                        prec, g->prec);
     if (flags & ~WD_FLAG_GAMMA5) return set_error(WD_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
-    const size_t n = static_cast<size_t>(g->V) * spinor_site_bytes(prec);
+    const size_t n = static_cast<size_t>(packed_sites(g->V)) * spinor_site_bytes(prec);
     if ((rc = check_device_range(in_dev, n, "in_dev")) != WD_OK) return rc;
     if ((rc = check_device_range(out_dev, n, "out_dev")) != WD_OK) return rc;
     if (overlaps(in_dev, n, out_dev, n)) return set_error(WD_ERR_INVALID_ARG, "in_dev and out_dev overlap");

@@ -22,36 +22,16 @@
 #define WD_XCD_GROUP -1       // tiles per XCD run; -1 picks automatically
 #endif
 #ifndef WD_DSLASH_KERNEL
-#define WD_DSLASH_KERNEL 2    // 2: t-marching, 0: split t-marching, 1: one site per lane
+#define WD_DSLASH_KERNEL 0    // 0: t-marching where the lattice allows it, 1: one site per lane
 #endif
 #ifndef WD_MARCH_THREADS
 #define WD_MARCH_THREADS 256  // target sites per t-marching tile
 #endif
-#ifndef WD_MARCH_BLOCKS
-#define WD_MARCH_BLOCKS 512   // target t-marching workgroups per launch
+#ifndef WD_MARCH_WG_PER_CU
+#define WD_MARCH_WG_PER_CU 2  // t-marching workgroups per CU aimed for (LDS permitting)
 #endif
 #ifndef WD_MARCH_XCD_GROUP
 #define WD_MARCH_XCD_GROUP 32 // preferred XCD run length of t-marching tiles
-#endif
-#ifndef WD_MARCH_EARLY_OUTER
-#define WD_MARCH_EARLY_OUTER 1 // z / off-tile y hops of t+1 at the start (1) or end (0) of step t
-#endif
-#ifndef WD_MARCH_WAVES
-#define WD_MARCH_WAVES 0      // occupancy hint for the t-marching kernel; 0 = none
-#endif
-#ifndef WD_WAVES_PER_EU
-#define WD_WAVES_PER_EU 0     // occupancy hint to the register allocator; 0 = none
-#endif
-
-#if WD_WAVES_PER_EU > 0
-#define WD_OCCUPANCY __attribute__((amdgpu_waves_per_eu(WD_WAVES_PER_EU)))
-#else
-#define WD_OCCUPANCY
-#endif
-#if WD_MARCH_WAVES > 0
-#define WD_MARCH_OCCUPANCY __attribute__((amdgpu_waves_per_eu(WD_MARCH_WAVES)))
-#else
-#define WD_MARCH_OCCUPANCY
 #endif
 
 namespace wd {
@@ -60,7 +40,8 @@ namespace {
 constexpr int kDslashBlock = WD_DSLASH_BLOCK;
 constexpr int kMarchMaxThreads = 256;
 constexpr int kMarchTargetThreads = WD_MARCH_THREADS;
-constexpr int kMarchTargetBlocks = WD_MARCH_BLOCKS;
+constexpr int kMarchWgPerCu = WD_MARCH_WG_PER_CU;
+constexpr int kNumCu = 256;
 constexpr int kMarchXcdGroup = WD_MARCH_XCD_GROUP;
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 
@@ -78,7 +59,7 @@ __device__ __forceinline__ int tile_of_block(int group) {
 }
 
 template <typename R, bool C12>
-__global__ __launch_bounds__(kDslashBlock) WD_OCCUPANCY void dslash_kernel(const typename Packed<R>::S* __restrict__ in,
+__global__ __launch_bounds__(kDslashBlock) void dslash_kernel(const typename Packed<R>::S* __restrict__ in,
                                                         typename Packed<R>::S* __restrict__ out,
                                                         const typename Packed<R>::L* __restrict__ links,
                                                         Geo geo, R diag, int gamma5, int group) {
@@ -155,7 +136,7 @@ __device__ __forceinline__ void outer_hops(const typename Packed<R>::S* __restri
 }
 
 template <typename R, bool C12>
-__global__ __launch_bounds__(kMarchMaxThreads) WD_MARCH_OCCUPANCY void dslash_march_kernel(
+__global__ __launch_bounds__(kMarchMaxThreads) void dslash_march_kernel(
     const typename Packed<R>::S* __restrict__ in, typename Packed<R>::S* __restrict__ out,
     const typename Packed<R>::L* __restrict__ links, Geo geo, R diag, int gamma5, MarchParams p) {
   using SV = typename Packed<R>::S;
@@ -228,8 +209,7 @@ __global__ __launch_bounds__(kMarchMaxThreads) WD_MARCH_OCCUPANCY void dslash_ma
       load_spinor(in, V, sn, psi);
       if (more) {
         lds_store_spinor(nxt, n, tid, psi);
-        if constexpr (WD_MARCH_EARLY_OUTER)
-          outer_hops<C12, R>(in, links, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, nacc);
+        outer_hops<C12, R>(in, links, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, nacc);
       }
       cx<R> h[6], g[6];
       project<3, -1>(psi, h);
@@ -266,130 +246,9 @@ __global__ __launch_bounds__(kMarchMaxThreads) WD_MARCH_OCCUPANCY void dslash_ma
         reconstruct_add<3, +1>(g, nacc);
       }
     }
-    if constexpr (!WD_MARCH_EARLY_OUTER)
-      if (more) outer_hops<C12, R>(in, links, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, nacc);
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = nacc[c];
     __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Split t-marching kernel: the same march with two lanes per site. The first
-// n lanes ("current") finish time t: the carried partial sum of t from LDS,
-// the forward t hop with their own psi(t+1), the x and in-tile y hops from
-// LDS, the epilogue and the store. The other n lanes ("next") meanwhile build
-// the carried partial sum of t+1: the backward t hop U_t(t)^dag P+ psi(t),
-// the z hops and the off-tile y hops, and hand it over through LDS. Each lane
-// keeps one accumulator, so the two halves fit twice the waves per CU.
-// ---------------------------------------------------------------------------
-
-template <typename R, bool C12>
-__global__ __launch_bounds__(2 * kMarchMaxThreads) WD_MARCH_OCCUPANCY void dslash_march2_kernel(
-    const typename Packed<R>::S* __restrict__ in, typename Packed<R>::S* __restrict__ out,
-    const typename Packed<R>::L* __restrict__ links, Geo geo, R diag, int gamma5, MarchParams p) {
-  using SV = typename Packed<R>::S;
-  constexpr int kPlanes = sizeof(R) == 8 ? 12 : 6;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int n = geo.X * p.ny;  // sites per tile; the workgroup has 2n lanes
-  SV* buf0 = reinterpret_cast<SV*>(smem);
-  SV* buf1 = buf0 + kPlanes * n;
-  SV* carry = buf1 + kPlanes * n;  // partial sums handed from "next" to "current" lanes
-  const long V = geo.V;
-
-  const bool next_lane = static_cast<int>(threadIdx.x) >= n;
-  const int tid = next_lane ? static_cast<int>(threadIdx.x) - n : static_cast<int>(threadIdx.x);
-  const int xl = tid % geo.X;
-  const int yl = tid / geo.X;
-  const int b = tile_of_block(p.group);
-  const int yt = b % p.ytiles;
-  const int z = (b / p.ytiles) % geo.Z;
-  const int tblk = b / (p.ytiles * geo.Z);
-  const int y = yt * p.ny + yl;
-  const int t0 = tblk * p.tb;
-  const int t1 = min(t0 + p.tb, geo.T);
-
-  const int s0 = xl + geo.X * (y + geo.Y * z);  // the site at t = 0
-  const int lxp = yl * geo.X + (xl + 1 == geo.X ? 0 : xl + 1);
-  const int lxm = yl * geo.X + (xl == 0 ? geo.X - 1 : xl - 1);
-  const bool whole_y = p.ny == geo.Y;
-  const bool y_fwd_out = !whole_y && yl + 1 == p.ny;
-  const bool y_bwd_out = !whole_y && yl == 0;
-  const int lyp = (yl + 1 == p.ny ? 0 : yl + 1) * geo.X + xl;
-  const int lym = (yl == 0 ? p.ny - 1 : yl - 1) * geo.X + xl;
-  const int dxm = xl == 0 ? geo.X - 1 : -1;
-  const int dyp = y + 1 == geo.Y ? -(geo.Y - 1) * geo.X : geo.X;
-  const int dym = y == 0 ? (geo.Y - 1) * geo.X : -geo.X;
-  const int dzp = z + 1 == geo.Z ? -(geo.Z - 1) * geo.XY : geo.XY;
-  const int dzm = z == 0 ? (geo.Z - 1) * geo.XY : -geo.XY;
-
-  // prologue: first slice into LDS; carried partial sum of t0
-  if (!next_lane) {
-    cx<R> psi[12];
-    load_spinor(in, V, s0 + t0 * geo.XYZ, psi);
-    lds_store_spinor(buf0, n, tid, psi);
-  } else {
-    cx<R> acc[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
-    const int tm = t0 == 0 ? geo.T - 1 : t0 - 1;
-    hop<3, +1, C12, R>(in, links, V, s0 + tm * geo.XYZ, s0 + tm * geo.XYZ, acc);
-    outer_hops<C12, R>(in, links, V, s0 + t0 * geo.XYZ, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym,
-                       acc);
-    lds_store_spinor(carry, n, tid, acc);
-  }
-  __syncthreads();
-
-  for (int t = t0; t < t1; ++t) {
-    SV* cur = ((t - t0) & 1) ? buf1 : buf0;
-    SV* nxt = ((t - t0) & 1) ? buf0 : buf1;
-    const int st = s0 + t * geo.XYZ;
-    const int sn = t + 1 == geo.T ? s0 : st + geo.XYZ;  // the site at t+1
-    const bool more = t + 1 < t1;
-    cx<R> acc[12];
-    if (!next_lane) {
-      lds_load_spinor(carry, n, tid, acc);
-      {
-        cx<R> psi[12];
-        load_spinor(in, V, sn, psi);
-        if (more) lds_store_spinor(nxt, n, tid, psi);
-        hop_psi<3, -1, C12, R>(psi, links, V, st, acc);
-      }
-      {
-        cx<R> psi[12];
-        lds_load_spinor(cur, n, lxp, psi);
-        hop_psi<0, -1, C12, R>(psi, links, V, st, acc);
-        lds_load_spinor(cur, n, lxm, psi);
-        hop_psi<0, +1, C12, R>(psi, links, V, st + dxm, acc);
-        if (!y_fwd_out) {
-          lds_load_spinor(cur, n, lyp, psi);
-          hop_psi<1, -1, C12, R>(psi, links, V, st, acc);
-        }
-        if (!y_bwd_out) {
-          lds_load_spinor(cur, n, lym, psi);
-          hop_psi<1, +1, C12, R>(psi, links, V, st + dym, acc);
-        }
-      }
-      {
-        cx<R> psi[12];
-        lds_load_spinor(cur, n, tid, psi);
-        cx<R> o[12];
-        epilogue(psi, acc, diag, gamma5, o);
-        store_spinor(out, V, st, o);
-      }
-    } else if (more) {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
-      {
-        cx<R> psi[12];
-        lds_load_spinor(cur, n, tid, psi);
-        hop_psi<3, +1, C12, R>(psi, links, V, st, acc);
-      }
-      outer_hops<C12, R>(in, links, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, acc);
-    }
-    __syncthreads();  // the carried sum of t has been read
-    if (next_lane && more) lds_store_spinor(carry, n, tid, acc);
-    __syncthreads();  // slice t+1 and the carried sum of t+1 are in LDS
   }
 }
 
@@ -406,9 +265,7 @@ size_t march_lds_bytes(int threads, size_t real_bytes) {
   return 2 * 24 * real_bytes * static_cast<size_t>(threads);  // two spinor slices
 }
 
-size_t march2_lds_bytes(int sites, size_t real_bytes) {
-  return 3 * 24 * real_bytes * static_cast<size_t>(sites);  // two slices + carried sums
-}
+
 
 MarchParams march_params(const Geo& geo, size_t real_bytes) {
   MarchParams p{0, 0, 0, 0};
@@ -416,14 +273,17 @@ MarchParams march_params(const Geo& geo, size_t real_bytes) {
   int ny = 0;
   for (int d = 1; d <= geo.Y; ++d)
     if (geo.Y % d == 0 && geo.X * d <= kMarchTargetThreads &&
-        march2_lds_bytes(geo.X * d, real_bytes) <= kLdsBytes)
+        march_lds_bytes(geo.X * d, real_bytes) <= kLdsBytes)
       ny = d;
   if (ny == 0 || geo.X * ny < 64) return p;
   p.ny = ny;
   p.ytiles = geo.Y / ny;
   const int planes = p.ytiles * geo.Z;
-  // enough workgroups to fill every CU once; t steps split evenly
-  int nt = (kMarchTargetBlocks + planes - 1) / planes;
+  // as many workgroups as fit on the chip at once (LDS decides how many per
+  // CU), t steps split evenly among the workgroups of one tile column
+  const int per_cu = static_cast<int>(kLdsBytes / march_lds_bytes(geo.X * ny, real_bytes));
+  const int target = kNumCu * (per_cu < kMarchWgPerCu ? per_cu : kMarchWgPerCu);
+  int nt = (target + planes - 1) / planes;
   nt = nt < 1 ? 1 : (nt > geo.T ? geo.T : nt);
   p.tb = (geo.T + nt - 1) / nt;
   const int nb = planes * ((geo.T + p.tb - 1) / p.tb);
@@ -455,28 +315,6 @@ hipError_t launch_march(const void* in, void* out, const void* links, const Geo&
 }
 
 template <typename R, bool C12>
-hipError_t launch_march2(const void* in, void* out, const void* links, const Geo& geo, R diag,
-                         int g5, const MarchParams& p, hipStream_t st) {
-  using SV = typename Packed<R>::S;
-  using LV = typename Packed<R>::L;
-  const int n = geo.X * p.ny;
-  const size_t lds = march2_lds_bytes(n, sizeof(R));
-  static std::atomic<int> attr_set{0};
-  if (!attr_set.load(std::memory_order_acquire)) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dslash_march2_kernel<R, C12>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(kLdsBytes));
-    if (e != hipSuccess) return e;
-    attr_set.store(1, std::memory_order_release);
-  }
-  const unsigned nb = static_cast<unsigned>(p.ytiles * geo.Z * ((geo.T + p.tb - 1) / p.tb));
-  dslash_march2_kernel<R, C12><<<nb, 2 * n, lds, st>>>(
-      static_cast<const SV*>(in), static_cast<SV*>(out), static_cast<const LV*>(links), geo, diag,
-      g5, p);
-  return hipGetLastError();
-}
-
-template <typename R, bool C12>
 hipError_t launch_site(const void* in, void* out, const void* links, const Geo& geo, R diag, int g5,
                        hipStream_t st) {
   using SV = typename Packed<R>::S;
@@ -496,8 +334,6 @@ hipError_t launch_typed(const void* in, void* out, const void* links, const Geo&
   const R diag = static_cast<R>(4.0 + mass);
   const MarchParams p = march_params(geo, sizeof(R));
   if (WD_DSLASH_KERNEL == 0 && p.ny > 0)
-    return launch_march2<R, C12>(in, out, links, geo, diag, g5, p, st);
-  if (WD_DSLASH_KERNEL == 2 && p.ny > 0)
     return launch_march<R, C12>(in, out, links, geo, diag, g5, p, st);
   return launch_site<R, C12>(in, out, links, geo, diag, g5, st);
 }

@@ -1,26 +1,49 @@
 // Packed device layouts of spinor and gauge fields, and their loads/stores.
 //
-// Every packed field is a structure of arrays with the site index fastest, so
-// that the 64 lanes of a wave, which hold 64 consecutive sites, read and write
-// contiguous 512 B - 1 KiB runs (Sec. II-B: the data layout decides how well
-// the stencil vectorises; here one lane per site plays the role of Grid's
-// one vector lane per virtual node, without any intra-vector permutes).
+// Every packed field is an array of structures of arrays: sites are grouped in
+// blocks of 64 consecutive sites (one wave), and inside a block each "plane"
+// (one 8- or 16-byte piece of every site's data) is a contiguous run of 64
+// elements. A wave's load of one plane is one contiguous 512 B - 1 KiB run,
+// and all planes of a block follow each other, so a wave streams its sites'
+// data as one contiguous region (Sec. II-B: the data layout decides how well
+// the stencil vectorises; one lane per site plays the role of Grid's one
+// vector lane per virtual node, without intra-vector permutes).
 //
-//  spinor, per right-hand side k (stride 24*V reals):
-//    FP64: 12 planes of V double2   plane c = 3*spin + colour
-//    FP32:  6 planes of V float4    plane j holds components 2j, 2j+1
-//  gauge, direction mu:
-//    FP64 full: 9 planes of V double2 per mu   plane 9*mu + 3*row + col
-//    FP64 c12 : 6 planes of V double2 per mu   rows 0 and 1 only
-//    FP32 full: 9 planes of V float2 per mu
-//    FP32 c12 : 3 planes of V float4 per mu    plane j holds entries 2j, 2j+1 of rows 0-1
+//  spinor, per right-hand side (stride packed_sites(V) * 24 reals):
+//    FP64: 12 planes of double2   plane c = 3*spin + colour
+//    FP32:  6 planes of float4    plane j holds components 2j, 2j+1
+//  gauge, all four directions in one block:
+//    FP64 full: 36 planes of double2   plane 9*mu + 3*row + col
+//    FP64 c12 : 24 planes of double2   plane 6*mu + 3*row + col, rows 0-1
+//    FP32 full: 36 planes of float2
+//    FP32 c12 : 12 planes of float4    plane 3*mu + j holds entries 2j, 2j+1 of rows 0-1
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include "cplx.h"
 
+// Sites per AoSoA block of a packed field (0: plain planes of V sites).
+#ifndef WD_LAYOUT_BLOCK
+#define WD_LAYOUT_BLOCK 64
+#endif
+
 namespace wd {
+
+constexpr int kLayoutBlock = WD_LAYOUT_BLOCK;
+
+// Sites a packed field of V sites is padded to.
+__host__ __device__ constexpr long packed_sites(long V) {
+  return kLayoutBlock > 0 ? (V + kLayoutBlock - 1) / kLayoutBlock * kLayoutBlock : V;
+}
+
+// Element index of plane c (of P planes per site) of site s in a packed field.
+__device__ __forceinline__ long pidx(long s, int c, int P, long V) {
+  if constexpr (kLayoutBlock > 0)
+    return ((s / kLayoutBlock) * P + c) * kLayoutBlock + (s % kLayoutBlock);
+  else
+    return c * V + s;
+}
 
 // Vector types of packed spinors (S) and links (L) per arithmetic precision.
 template <typename R>
@@ -46,7 +69,7 @@ __device__ __forceinline__ void load_spinor(const double2* __restrict__ p, long 
                                             cx<double> (&v)[12]) {
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
-    const double2 t = p[c * V + s];
+    const double2 t = p[pidx(s, c, 12, V)];
     v[c] = {t.x, t.y};
   }
 }
@@ -55,7 +78,7 @@ __device__ __forceinline__ void load_spinor(const float4* __restrict__ p, long V
                                             cx<float> (&v)[12]) {
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    const float4 t = p[j * V + s];
+    const float4 t = p[pidx(s, j, 6, V)];
     v[2 * j] = {t.x, t.y};
     v[2 * j + 1] = {t.z, t.w};
   }
@@ -66,7 +89,7 @@ __device__ __forceinline__ void store_spinor(double2* __restrict__ p, long V, in
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
     const nd2 t = {v[c].re, v[c].im};
-    __builtin_nontemporal_store(t, reinterpret_cast<nd2*>(p + c * V + s));
+    __builtin_nontemporal_store(t, reinterpret_cast<nd2*>(p + pidx(s, c, 12, V)));
   }
 }
 
@@ -75,7 +98,7 @@ __device__ __forceinline__ void store_spinor(float4* __restrict__ p, long V, int
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     const nf4 t = {v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im};
-    __builtin_nontemporal_store(t, reinterpret_cast<nf4*>(p + j * V + s));
+    __builtin_nontemporal_store(t, reinterpret_cast<nf4*>(p + pidx(s, j, 6, V)));
   }
 }
 
@@ -124,7 +147,7 @@ __device__ __forceinline__ void load_link(const double2* __restrict__ p, long V,
   constexpr int n = C12 ? 6 : 9;
 #pragma unroll
   for (int k = 0; k < n; ++k) {
-    const double2 t = p[(mu * n + k) * V + s];
+    const double2 t = p[pidx(s, mu * n + k, 4 * n, V)];
     u[k] = {t.x, t.y};
   }
   if constexpr (C12) rebuild_row2(u);
@@ -137,7 +160,7 @@ __device__ __forceinline__ void load_link(const float2* __restrict__ p, long V, 
     const float4* q = reinterpret_cast<const float4*>(p);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const float4 t = q[(mu * 3 + j) * V + s];
+      const float4 t = q[pidx(s, mu * 3 + j, 12, V)];
       u[2 * j] = {t.x, t.y};
       u[2 * j + 1] = {t.z, t.w};
     }
@@ -145,7 +168,7 @@ __device__ __forceinline__ void load_link(const float2* __restrict__ p, long V, 
   } else {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const float2 t = p[(mu * 9 + k) * V + s];
+      const float2 t = p[pidx(s, mu * 9 + k, 36, V)];
       u[k] = {t.x, t.y};
     }
   }

@@ -18,18 +18,19 @@ __global__ __launch_bounds__(kBlock) void pack_spinor_kernel(const double2* __re
   if (i >= total) return;
   const long k = i / V;
   const long s = i - k * V;
+  const long PV = packed_sites(V);
   const double2* src = canon + i * 12;
   if constexpr (sizeof(R) == 8) {
-    double2* d = dst + k * 12 * V;
+    double2* d = dst + k * 12 * PV;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) d[c * V + s] = src[c];
+    for (int c = 0; c < 12; ++c) d[pidx(s, c, 12, V)] = src[c];
   } else {
-    float4* d = dst + k * 6 * V;
+    float4* d = dst + k * 6 * PV;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       const double2 a = src[2 * j];
       const double2 b = src[2 * j + 1];
-      d[j * V + s] = make_float4(static_cast<float>(a.x), static_cast<float>(a.y),
+      d[pidx(s, j, 6, V)] = make_float4(static_cast<float>(a.x), static_cast<float>(a.y),
                                  static_cast<float>(b.x), static_cast<float>(b.y));
     }
   }
@@ -42,16 +43,17 @@ __global__ __launch_bounds__(kBlock) void unpack_spinor_kernel(
   if (i >= total) return;
   const long k = i / V;
   const long s = i - k * V;
+  const long PV = packed_sites(V);
   double2* d = canon + i * 12;
   if constexpr (sizeof(R) == 8) {
-    const double2* p = src + k * 12 * V;
+    const double2* p = src + k * 12 * PV;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) d[c] = p[c * V + s];
+    for (int c = 0; c < 12; ++c) d[c] = p[pidx(s, c, 12, V)];
   } else {
-    const float4* p = src + k * 6 * V;
+    const float4* p = src + k * 6 * PV;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      const float4 t = p[j * V + s];
+      const float4 t = p[pidx(s, j, 6, V)];
       d[2 * j] = make_double2(t.x, t.y);
       d[2 * j + 1] = make_double2(t.z, t.w);
     }
@@ -72,21 +74,21 @@ __global__ __launch_bounds__(kBlock) void pack_gauge_kernel(const double2* __res
     constexpr int n = C12 ? 6 : 9;
     double2* d = static_cast<double2*>(dst);
 #pragma unroll
-    for (int k = 0; k < n; ++k) d[(mu * n + k) * V + s] = src[k];
+    for (int k = 0; k < n; ++k) d[pidx(s, mu * n + k, 4 * n, V)] = src[k];
   } else if constexpr (C12) {
     float4* d = static_cast<float4*>(dst);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       const double2 a = src[2 * j];
       const double2 b = src[2 * j + 1];
-      d[(mu * 3 + j) * V + s] = make_float4(static_cast<float>(a.x), static_cast<float>(a.y),
+      d[pidx(s, mu * 3 + j, 12, V)] = make_float4(static_cast<float>(a.x), static_cast<float>(a.y),
                                             static_cast<float>(b.x), static_cast<float>(b.y));
     }
   } else {
     float2* d = static_cast<float2*>(dst);
 #pragma unroll
     for (int k = 0; k < 9; ++k)
-      d[(mu * 9 + k) * V + s] = make_float2(static_cast<float>(src[k].x), static_cast<float>(src[k].y));
+      d[pidx(s, mu * 9 + k, 36, V)] = make_float2(static_cast<float>(src[k].x), static_cast<float>(src[k].y));
   }
 }
 
