@@ -139,6 +139,61 @@ WD_API int wd_spinor_export(const wd_gauge* g, const void* src_dev, int32_t prec
 WD_API int dslash_apply(const wd_gauge* g, double mass, const void* in_dev, void* out_dev,
                  int32_t prec, int32_t flags, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Conjugate gradient on the normal equations D^dag D x = b.
+ *
+ * Sec. II-A of the paper names iterative solvers such as conjugate gradient
+ * as where lattice QCD spends its time, dominated by the Dirac operator
+ * applied to a quark field. D^dag D = Q^2 with the Hermitian Q = gamma5 D, so
+ * every iteration applies dslash twice. With inner = WD_FP32 the iterations
+ * run on FP32 fields (g_lo) while the solution is accumulated in FP64 and the
+ * residual is recomputed in FP64 (b - D^dag D x with g_hi) whenever the FP32
+ * residual has dropped by delta since the last recompute or claims
+ * convergence ("reliable updates"); convergence is always decided on that FP64
+ * true residual.
+ * ------------------------------------------------------------------------ */
+
+typedef struct wd_cg_params {
+  double tol;          /* stop when |b - D^dag D x| <= tol |b| (FP64 true residual) */
+  int32_t max_iter;    /* >= 1; iterations of the inner loop (each: two dslash) */
+  int32_t inner;       /* WD_FP64 (plain CG) or WD_FP32 (mixed precision) */
+  double delta;        /* reliable-update threshold in (0, 1); used with WD_FP32 */
+  int32_t check_every; /* >= 1; iterations between host checks of the residual */
+  int32_t x0_given;    /* nonzero: start from the contents of x_dev, else x0 = 0 */
+} wd_cg_params;
+
+typedef struct wd_cg_stats {
+  int32_t status;            /* WD_OK, WD_ERR_NOT_CONVERGED or WD_ERR_NUMERIC */
+  int32_t iters;             /* inner iterations run */
+  int32_t reliable_updates;  /* FP64 residual recomputations */
+  int32_t reserved;
+  double true_rel_residual;  /* |b - D^dag D x| / |b| at the last recompute */
+  double seconds;            /* wall time of the whole call */
+} wd_cg_stats;
+
+/* Bytes of device workspace cg_solve_normal needs for nrhs right-hand sides
+ * (1..16) on a lattice of extents dims with the given inner precision; 0 for
+ * invalid arguments. */
+WD_API size_t cg_workspace_bytes(const int32_t dims[4], int32_t nrhs, int32_t inner);
+
+/* Solves D(m_k)^dag D(m_k) x_k = b_k for k < nrhs (1..16), each right-hand
+ * side with its own mass masses_host[k]. b_dev and x_dev hold nrhs packed FP64
+ * spinors of g_hi's lattice (wd_spinor_bytes(dims, WD_FP64, nrhs) bytes each;
+ * x_dev is the output, and the start vector if params->x0_given). g_hi is an
+ * FP64 gauge handle; g_lo an FP32 handle of the same lattice when
+ * params->inner == WD_FP32 (ignored otherwise, may be NULL). ws_dev:
+ * cg_workspace_bytes(...) bytes of caller-owned device memory, not
+ * overlapping b_dev or x_dev. stats_host: nrhs entries (may be NULL).
+ * Synchronous: work is enqueued on stream and the call returns when every
+ * right-hand side has converged, failed or used max_iter iterations.
+ * Returns WD_OK if all converged, else WD_ERR_NOT_CONVERGED or
+ * WD_ERR_NUMERIC (per right-hand side detail in stats_host), or an argument
+ * or device error. */
+WD_API int cg_solve_normal(const wd_gauge* g_hi, const wd_gauge* g_lo, const double* masses_host,
+                           int32_t nrhs, const void* b_dev, void* x_dev,
+                           const wd_cg_params* params, wd_cg_stats* stats_host, void* ws_dev,
+                           size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 } /* extern "C" */
 #endif

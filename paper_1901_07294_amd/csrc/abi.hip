@@ -42,8 +42,6 @@ size_t gauge_site_bytes(int prec, int c12) {
   }
 }
 
-namespace {
-
 constexpr long kMaxSites = (1L << 31) / 12 - 1;  // keeps plane offsets in range
 
 // Validates dims; on success stores the volume in *V.
@@ -120,7 +118,6 @@ int launch_status(hipError_t e, const char* what) {
   return set_error(WD_ERR_DEVICE, "%s: launch failed: %s", what, hipGetErrorString(e));
 }
 
-}  // namespace
 }  // namespace wd
 
 using namespace wd;

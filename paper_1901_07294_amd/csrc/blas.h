@@ -1,0 +1,52 @@
+// Vector kernels of the CG solver (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "wilson.h"
+
+namespace wd {
+
+constexpr int kMaxRhs = 16;         // right-hand sides per solve
+constexpr int kMaxPartials = 1024;  // per-workgroup partial sums per right-hand side
+
+// The right-hand sides a launch works on: one grid row (blockIdx.y) each.
+struct RhsSet {
+  int n;
+  int idx[kMaxRhs];
+};
+
+// Per right-hand side scalars in device memory (doubles).
+enum : int {
+  kRr = 0,      // <r, r> of the current residual
+  kPap = 1,     // <p, A p>
+  kAlpha = 2,
+  kBeta = 3,
+  kRrMax = 4,   // largest <r, r> since the last true residual
+  kRrTrue = 5,  // <r, r> of the last true residual
+  kB2 = 6,      // <b, b>
+  kFlag = 7,    // nonzero: a non-finite or non-positive quantity appeared
+  kScalars = 8
+};
+
+// What a reduction's result updates (finalize modes).
+enum : int { kFinPap = 0, kFinIterRr = 1, kFinTrueRr = 2, kFinNorm = 3 };
+
+// Workgroups of a reduction over n elements (fixed for a lattice).
+int reduction_blocks(long n);
+
+// n: 16-byte elements per right-hand side of the vectors in precision prec;
+// nhi: FP64 elements per right-hand side; V: lattice sites.
+hipError_t blas_norm2(const void* v, int prec, long n, long V, const RhsSet& set, double* partials,
+                      double* scal, int mode, hipStream_t st);
+hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nhi,
+                          long V, const RhsSet& set, double* partials, double* scal, hipStream_t st);
+hipError_t blas_update_p(void* p, const void* r, int prec, long n, const RhsSet& set,
+                         const double* scal, hipStream_t st);
+hipError_t blas_residual(void* r, const void* b, long n, long V, const RhsSet& set, double* partials,
+                         double* scal, hipStream_t st);
+hipError_t blas_demote(void* lo, const void* hi, long n, long nhi, const RhsSet& set, hipStream_t st);
+hipError_t blas_copy(void* dst, const void* src, int prec, long n, const RhsSet& set, hipStream_t st);
+hipError_t blas_zero(void* dst, int prec, long n, const RhsSet& set, hipStream_t st);
+
+}  // namespace wd

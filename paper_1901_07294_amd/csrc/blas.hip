@@ -1,0 +1,342 @@
+// Vector kernels of the conjugate-gradient solver: fused updates and
+// deterministic reductions over packed spinor fields.
+//
+// A packed field (fields.h) is a flat array of 16-byte elements: 12 per site
+// in FP64 (double2), 6 per site in FP32 (float4), in blocks of 64 sites. The
+// elementwise kernels walk that flat array; the reductions skip the padding
+// sites of the last block. Every reduction is two-stage with a fixed
+// assignment of elements to threads and a fixed combination order, so a sum
+// depends only on the lattice, never on how many right-hand sides are in
+// flight or on timing: results are bitwise reproducible.
+#include "blas.h"
+#include "fields.h"
+
+namespace wd {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of v over the workgroup, combined in a fixed order; valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double part[kThreads / 64];
+  v = wave_sum(v);
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) part[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kThreads / 64; ++i) s += part[i];
+  return s;
+}
+
+__device__ __forceinline__ double norm2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double norm2(float4 a) {
+  return static_cast<double>(a.x) * a.x + static_cast<double>(a.y) * a.y +
+         static_cast<double>(a.z) * a.z + static_cast<double>(a.w) * a.w;
+}
+
+// Is flat element e of a packed field of P elements per site a real site?
+template <int P>
+__device__ __forceinline__ bool real_site(long e, long V) {
+  return (e / (P * 64)) * 64 + (e % 64) < V;
+}
+
+template <typename T>
+struct Elems;
+template <>
+struct Elems<double2> {
+  static constexpr int P = 12;
+};
+template <>
+struct Elems<float4> {
+  static constexpr int P = 6;
+};
+
+// ---------------------------------------------------------------- partials
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void norm2_partial_kernel(const T* __restrict__ v, long n,
+                                                                 long V, RhsSet set,
+                                                                 double* __restrict__ partials) {
+  const int slot = blockIdx.y;
+  const T* x = v + set.idx[slot] * n;
+  double s = 0.0;
+  for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
+       e += static_cast<long>(gridDim.x) * kThreads)
+    if (real_site<Elems<T>::P>(e, V)) s += norm2(x[e]);
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[set.idx[slot] * gridDim.x + blockIdx.x] = s;
+}
+
+// x_hi += alpha p ; r -= alpha Ap ; partial |r|^2   (alpha from the scalars)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void update_xr_kernel(double2* __restrict__ x, T* __restrict__ r,
+                                                             const T* __restrict__ p,
+                                                             const T* __restrict__ ap, long n, long nhi,
+                                                             long V, RhsSet set,
+                                                             const double* __restrict__ scal,
+                                                             double* __restrict__ partials) {
+  const int k = set.idx[blockIdx.y];
+  const double alpha = scal[k * kScalars + kAlpha];
+  double2* xk = x + k * nhi;
+  T* rk = r + k * n;
+  const T* pk = p + k * n;
+  const T* apk = ap + k * n;
+  double s = 0.0;
+  for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
+       e += static_cast<long>(gridDim.x) * kThreads) {
+    const T pe = pk[e];
+    T re = rk[e];
+    const T ae = apk[e];
+    if constexpr (Elems<T>::P == 12) {
+      double2 xe = xk[e];
+      xe.x += alpha * pe.x;
+      xe.y += alpha * pe.y;
+      xk[e] = xe;
+      re.x -= alpha * ae.x;
+      re.y -= alpha * ae.y;
+    } else {
+      // FP32 element j of a block holds FP64 elements 2j and 2j+1 of the same sites
+      const long blk = e / (6 * 64);
+      const long j = (e / 64) % 6;
+      const long lane = e % 64;
+      const long h0 = (blk * 12 + 2 * j) * 64 + lane;
+      double2 x0 = xk[h0];
+      double2 x1 = xk[h0 + 64];
+      x0.x += alpha * pe.x;
+      x0.y += alpha * pe.y;
+      x1.x += alpha * pe.z;
+      x1.y += alpha * pe.w;
+      xk[h0] = x0;
+      xk[h0 + 64] = x1;
+      const float a = static_cast<float>(alpha);
+      re.x -= a * ae.x;
+      re.y -= a * ae.y;
+      re.z -= a * ae.z;
+      re.w -= a * ae.w;
+    }
+    rk[e] = re;
+    if (real_site<Elems<T>::P>(e, V)) s += norm2(re);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
+}
+
+// p = r + beta p
+template <typename T>
+__global__ __launch_bounds__(kThreads) void update_p_kernel(T* __restrict__ p, const T* __restrict__ r,
+                                                            long n, RhsSet set,
+                                                            const double* __restrict__ scal) {
+  const int k = set.idx[blockIdx.y];
+  const double beta = scal[k * kScalars + kBeta];
+  T* pk = p + k * n;
+  const T* rk = r + k * n;
+  for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
+       e += static_cast<long>(gridDim.x) * kThreads) {
+    T pe = pk[e];
+    const T re = rk[e];
+    if constexpr (Elems<T>::P == 12) {
+      pe.x = re.x + beta * pe.x;
+      pe.y = re.y + beta * pe.y;
+    } else {
+      const float b = static_cast<float>(beta);
+      pe.x = re.x + b * pe.x;
+      pe.y = re.y + b * pe.y;
+      pe.z = re.z + b * pe.z;
+      pe.w = re.w + b * pe.w;
+    }
+    pk[e] = pe;
+  }
+}
+
+// r = b - r (r holds A x on entry), partial |r|^2
+__global__ __launch_bounds__(kThreads) void residual_kernel(double2* __restrict__ r,
+                                                            const double2* __restrict__ b, long n,
+                                                            long V, RhsSet set,
+                                                            double* __restrict__ partials) {
+  const int k = set.idx[blockIdx.y];
+  double2* rk = r + k * n;
+  const double2* bk = b + k * n;
+  double s = 0.0;
+  for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
+       e += static_cast<long>(gridDim.x) * kThreads) {
+    const double2 be = bk[e];
+    double2 re = rk[e];
+    re.x = be.x - re.x;
+    re.y = be.y - re.y;
+    rk[e] = re;
+    if (real_site<12>(e, V)) s += norm2(re);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
+}
+
+// lo = FP32(hi), over FP32 elements
+__global__ __launch_bounds__(kThreads) void demote_kernel(float4* __restrict__ lo,
+                                                          const double2* __restrict__ hi, long n,
+                                                          long nhi, RhsSet set) {
+  const int k = set.idx[blockIdx.y];
+  float4* lk = lo + k * n;
+  const double2* hk = hi + k * nhi;
+  for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
+       e += static_cast<long>(gridDim.x) * kThreads) {
+    const long blk = e / (6 * 64);
+    const long j = (e / 64) % 6;
+    const long lane = e % 64;
+    const long h0 = (blk * 12 + 2 * j) * 64 + lane;
+    const double2 a = hk[h0];
+    const double2 c = hk[h0 + 64];
+    lk[e] = make_float4(static_cast<float>(a.x), static_cast<float>(a.y), static_cast<float>(c.x),
+                        static_cast<float>(c.y));
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void copy_kernel(T* __restrict__ dst, const T* __restrict__ src,
+                                                        long n, RhsSet set) {
+  const int k = set.idx[blockIdx.y];
+  for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
+       e += static_cast<long>(gridDim.x) * kThreads)
+    dst[k * n + e] = src[k * n + e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void zero_kernel(T* __restrict__ dst, long n, RhsSet set) {
+  const int k = set.idx[blockIdx.y];
+  T z;
+  memset(&z, 0, sizeof(T));
+  for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
+       e += static_cast<long>(gridDim.x) * kThreads)
+    dst[k * n + e] = z;
+}
+
+// One workgroup per right-hand side: sum its partials in a fixed order and
+// update the scalars. Non-finite or non-positive curvature raises kFlag.
+__global__ __launch_bounds__(kThreads) void finalize_kernel(const double* __restrict__ partials,
+                                                            int nparts, RhsSet set, int mode,
+                                                            double* __restrict__ scal) {
+  const int k = set.idx[blockIdx.x];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kThreads) s += partials[k * nparts + i];
+  s = block_sum(s);
+  if (threadIdx.x != 0) return;
+  double* sc = scal + k * kScalars;
+  if (!isfinite(s)) sc[kFlag] = 1.0;
+  switch (mode) {
+    case kFinPap:  // <p, A p> = |Q p|^2 ; alpha = rr / pAp
+      sc[kPap] = s;
+      if (!(s > 0.0)) {
+        sc[kAlpha] = 0.0;
+        if (sc[kRr] > 0.0) sc[kFlag] = 1.0;
+      } else {
+        sc[kAlpha] = sc[kRr] / s;
+      }
+      break;
+    case kFinIterRr:  // iterated residual; beta = rr_new / rr
+      sc[kBeta] = sc[kRr] > 0.0 ? s / sc[kRr] : 0.0;
+      sc[kRr] = s;
+      if (s > sc[kRrMax]) sc[kRrMax] = s;
+      break;
+    case kFinTrueRr:  // true residual after a reliable update
+      sc[kRr] = s;
+      sc[kRrMax] = s;
+      sc[kRrTrue] = s;
+      break;
+    case kFinNorm:  // plain norm (|b|^2)
+      sc[kB2] = s;
+      break;
+  }
+}
+
+dim3 grid(long n, int nset) {
+  long nb = (n + kThreads * 4 - 1) / (kThreads * 4);
+  if (nb > kMaxPartials) nb = kMaxPartials;
+  if (nb < 1) nb = 1;
+  return dim3(static_cast<unsigned>(nb), static_cast<unsigned>(nset));
+}
+
+}  // namespace
+
+int reduction_blocks(long n) { return static_cast<int>(grid(n, 1).x); }
+
+hipError_t blas_norm2(const void* v, int prec, long n, long V, const RhsSet& set, double* partials,
+                      double* scal, int mode, hipStream_t st) {
+  const dim3 g = grid(n, set.n);
+  if (prec == WD_FP64)
+    norm2_partial_kernel<double2><<<g, kThreads, 0, st>>>(static_cast<const double2*>(v), n, V, set, partials);
+  else
+    norm2_partial_kernel<float4><<<g, kThreads, 0, st>>>(static_cast<const float4*>(v), n, V, set, partials);
+  finalize_kernel<<<set.n, kThreads, 0, st>>>(partials, static_cast<int>(g.x), set, mode, scal);
+  return hipGetLastError();
+}
+
+hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nhi,
+                          long V, const RhsSet& set, double* partials, double* scal, hipStream_t st) {
+  const dim3 g = grid(n, set.n);
+  auto* xh = static_cast<double2*>(x);
+  if (prec == WD_FP64)
+    update_xr_kernel<double2><<<g, kThreads, 0, st>>>(xh, static_cast<double2*>(r),
+                                                       static_cast<const double2*>(p),
+                                                       static_cast<const double2*>(ap), n, nhi, V,
+                                                       set, scal, partials);
+  else
+    update_xr_kernel<float4><<<g, kThreads, 0, st>>>(xh, static_cast<float4*>(r),
+                                                      static_cast<const float4*>(p),
+                                                      static_cast<const float4*>(ap), n, nhi, V,
+                                                      set, scal, partials);
+  finalize_kernel<<<set.n, kThreads, 0, st>>>(partials, static_cast<int>(g.x), set, kFinIterRr, scal);
+  return hipGetLastError();
+}
+
+hipError_t blas_update_p(void* p, const void* r, int prec, long n, const RhsSet& set,
+                         const double* scal, hipStream_t st) {
+  const dim3 g = grid(n, set.n);
+  if (prec == WD_FP64)
+    update_p_kernel<double2><<<g, kThreads, 0, st>>>(static_cast<double2*>(p),
+                                                      static_cast<const double2*>(r), n, set, scal);
+  else
+    update_p_kernel<float4><<<g, kThreads, 0, st>>>(static_cast<float4*>(p),
+                                                     static_cast<const float4*>(r), n, set, scal);
+  return hipGetLastError();
+}
+
+hipError_t blas_residual(void* r, const void* b, long n, long V, const RhsSet& set, double* partials,
+                         double* scal, hipStream_t st) {
+  const dim3 g = grid(n, set.n);
+  residual_kernel<<<g, kThreads, 0, st>>>(static_cast<double2*>(r), static_cast<const double2*>(b), n,
+                                          V, set, partials);
+  finalize_kernel<<<set.n, kThreads, 0, st>>>(partials, static_cast<int>(g.x), set, kFinTrueRr, scal);
+  return hipGetLastError();
+}
+
+hipError_t blas_demote(void* lo, const void* hi, long n, long nhi, const RhsSet& set, hipStream_t st) {
+  demote_kernel<<<grid(n, set.n), kThreads, 0, st>>>(static_cast<float4*>(lo),
+                                                     static_cast<const double2*>(hi), n, nhi, set);
+  return hipGetLastError();
+}
+
+hipError_t blas_copy(void* dst, const void* src, int prec, long n, const RhsSet& set, hipStream_t st) {
+  if (prec == WD_FP64)
+    copy_kernel<double2><<<grid(n, set.n), kThreads, 0, st>>>(static_cast<double2*>(dst),
+                                                              static_cast<const double2*>(src), n, set);
+  else
+    copy_kernel<float4><<<grid(n, set.n), kThreads, 0, st>>>(static_cast<float4*>(dst),
+                                                             static_cast<const float4*>(src), n, set);
+  return hipGetLastError();
+}
+
+hipError_t blas_zero(void* dst, int prec, long n, const RhsSet& set, hipStream_t st) {
+  if (prec == WD_FP64)
+    zero_kernel<double2><<<grid(n, set.n), kThreads, 0, st>>>(static_cast<double2*>(dst), n, set);
+  else
+    zero_kernel<float4><<<grid(n, set.n), kThreads, 0, st>>>(static_cast<float4*>(dst), n, set);
+  return hipGetLastError();
+}
+
+}  // namespace wd

@@ -46,6 +46,14 @@ inline Geo make_geo(const int32_t d[4]) {
   return g;
 }
 
+// Argument checks shared by the entry points (they set the last error).
+int check_dims(const int32_t dims[4], long* V);
+int check_prec(int prec);
+int check_device_range(const void* p, size_t bytes, const char* what);
+bool overlaps(const void* a, size_t na, const void* b, size_t nb);
+int check_gauge(const wd_gauge* g);
+int launch_status(hipError_t e, const char* what);
+
 // Bytes per site of packed fields.
 size_t spinor_site_bytes(int prec);
 size_t gauge_site_bytes(int prec, int c12);

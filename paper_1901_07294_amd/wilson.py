@@ -39,6 +39,23 @@ WD_FLAG_GAMMA5 = 1
 STATUS_NAMES = {v: k for k, v in dict(globals()).items()
                 if k.startswith("WD_ERR_") or k in ("WD_OK", "WD_PENDING")}
 
+
+class wd_cg_params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("inner", ctypes.c_int32),
+                ("delta", ctypes.c_double), ("check_every", ctypes.c_int32),
+                ("x0_given", ctypes.c_int32)]
+
+
+class wd_cg_stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("reliable_updates", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"status": self.status, "iters": self.iters,
+                "reliable_updates": self.reliable_updates,
+                "true_rel_residual": self.true_rel_residual, "seconds": self.seconds}
+
 # Exported C symbols and their ctypes signatures.
 _i32 = ctypes.c_int32
 _vp = ctypes.c_void_p
@@ -54,6 +71,10 @@ SIGNATURES = {
     "wd_spinor_import": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp]),
     "wd_spinor_export": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp]),
     "dslash_apply": (ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp, _i32, _i32, _vp]),
+    "cg_workspace_bytes": (ctypes.c_size_t, [_dims_t, _i32, _i32]),
+    "cg_solve_normal": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp,
+                                       ctypes.POINTER(wd_cg_params), ctypes.POINTER(wd_cg_stats),
+                                       _vp, ctypes.c_size_t, _vp]),
 }
 
 
@@ -200,3 +221,26 @@ def wd_spinor_export(g, src, prec, nrhs, canon, stream=None) -> int:
 def dslash_apply(g, mass, inp, out, prec, flags=0, stream=None) -> int:
     return _check("dslash_apply", _L().dslash_apply(
         _h(g), float(mass), _ptr(inp), _ptr(out), prec, flags, _stream(stream)))
+
+
+def cg_workspace_bytes(dims, nrhs, inner) -> int:
+    return _L().cg_workspace_bytes(_dims(dims), nrhs, inner)
+
+
+def cg_solve_normal(g_hi, g_lo, masses, nrhs, b, x, params, ws, ws_bytes=None, stream=None,
+                    check=True):
+    """Calls cg_solve_normal; returns (status, [per right-hand side stats dicts]).
+
+    params: a wd_cg_params or a dict of its fields. With check=True a negative
+    status other than WD_ERR_NOT_CONVERGED / WD_ERR_NUMERIC raises WilsonError.
+    """
+    if isinstance(params, dict):
+        params = wd_cg_params(**params)
+    m = (ctypes.c_double * nrhs)(*[float(v) for v in masses])
+    stats = (wd_cg_stats * max(1, nrhs))()
+    nb = _nbytes(ws) if ws_bytes is None else int(ws_bytes)
+    rc = _L().cg_solve_normal(_h(g_hi), _h(g_lo) if g_lo is not None else None, m, nrhs, _ptr(b),
+                              _ptr(x), ctypes.byref(params), stats, _ptr(ws), nb, _stream(stream))
+    if check and rc < 0 and rc not in (WD_ERR_NOT_CONVERGED, WD_ERR_NUMERIC):
+        raise WilsonError("cg_solve_normal", rc, _L().wd_last_error().decode())
+    return rc, [stats[k].as_dict() for k in range(nrhs)]

@@ -1,0 +1,180 @@
+"""GPU conjugate gradient on D^dag D x = b against the oracle.
+
+Every solution is checked by the oracle itself: the true residual
+|b - D^dag D x| / |b| is recomputed in FP64 on the CPU, and x is compared with
+the oracle's own CG solution (or a dense solve on 2^4) within the condition
+number times the tolerance.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import lattice_inputs as li
+import oracle
+import paper_1901_07294_amd.wilson as w
+from paper_1901_07294_amd.buffers import DeviceGauge
+
+from gpu_util import rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    torch.cuda.set_device(0)
+
+
+def true_rel_residual(U, m, b, x):
+    r = b - oracle.normal_op(U, m, x)
+    return float(np.linalg.norm(r) / np.linalg.norm(b))
+
+
+def solve(U, masses, bs, inner, tol=1e-10, max_iter=20000, delta=0.1, check_every=4, x0=None):
+    """Solve through the C ABI; bs: [nrhs, T, Z, Y, X, 4, 3]. Returns (rc, xs, stats)."""
+    nrhs = len(masses)
+    ghi = DeviceGauge(U, w.WD_FP64)
+    glo = DeviceGauge(U, w.WD_FP32) if inner == w.WD_FP32 else None
+    b = ghi.pack(bs, nrhs=nrhs)
+    x = ghi.pack(x0, nrhs=nrhs) if x0 is not None else ghi.spinor(nrhs)
+    ws = torch.empty(w.cg_workspace_bytes(ghi.dims, nrhs, inner), dtype=torch.uint8, device="cuda")
+    params = dict(tol=tol, max_iter=max_iter, inner=inner, delta=delta, check_every=check_every,
+                  x0_given=int(x0 is not None))
+    rc, stats = w.cg_solve_normal(ghi.handle, glo.handle if glo else None, masses, nrhs, b, x,
+                                  params, ws)
+    xs = ghi.unpack(x, nrhs=nrhs)
+    return rc, (xs if nrhs > 1 else xs[None]), stats, x
+
+
+INNER = {"fp64": w.WD_FP64, "fp32": w.WD_FP32}
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_cg_dense_2222(inner):
+    dims = (2, 2, 2, 2)
+    U = li.near_unity_gauge(dims, 91, 0.3)
+    b = li.gaussian_spinor(dims, 92)
+    m = 0.05
+    rc, xs, stats, _ = solve(U, [m], b[None], INNER[inner], tol=1e-12)
+    assert rc == w.WD_OK, stats
+    M = oracle.dense_matrix(U, m)
+    x_ref = np.linalg.solve(M.conj().T @ M, b.ravel())
+    kappa = np.linalg.cond(M.conj().T @ M)
+    assert true_rel_residual(U, m, b, xs[0]) <= 1e-12
+    assert rel(xs[0].ravel(), x_ref) <= kappa * 1e-12
+    assert stats[0]["true_rel_residual"] <= 1e-12
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_cg_matches_oracle_cg(inner):
+    dims = (8, 4, 4, 6)
+    U = li.near_unity_gauge(dims, 4001, 0.3)
+    b = li.gaussian_spinor(dims, 4100)
+    m = 0.05
+    rc, xs, stats, _ = solve(U, [m], b[None], INNER[inner])
+    assert rc == w.WD_OK, stats
+    x_ref, it_ref, res_ref = oracle.cg_normal(U, m, b, tol=1e-10)
+    res = true_rel_residual(U, m, b, xs[0])
+    assert res <= 1e-10
+    assert abs(res - stats[0]["true_rel_residual"]) <= 1e-3 * 1e-10 + 1e-14
+    # |x - x_ref| / |x_ref| <= kappa * (tol_gpu + tol_ref); kappa <= ((8+m)/m)^2 bounded loosely
+    assert rel(xs[0], x_ref) <= 1e-4
+    if inner == "fp32":
+        assert stats[0]["reliable_updates"] >= 2
+    print("iters", stats[0]["iters"], "oracle iters", it_ref, "updates", stats[0]["reliable_updates"])
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_cg_24_4_near_unity(inner):
+    """The mixed-precision solver configuration: 24^4, m = 0.05, eps = 0.3, tol 1e-10."""
+    dims = (24, 24, 24, 24)
+    U = li.near_unity_gauge(dims, li.seed_gauge(4), 0.3)
+    b = li.gaussian_spinor(dims, li.seed_spinor(4))
+    m = 0.05
+    print(f"case cg 24^4 inner={inner}", flush=True)
+    rc, xs, stats, _ = solve(U, [m], b[None], INNER[inner], check_every=8)
+    assert rc == w.WD_OK, stats
+    assert true_rel_residual(U, m, b, xs[0]) <= 1e-10
+    print(stats[0])
+
+
+def test_cg_multi_rhs_equals_alone():
+    """Each right-hand side of a batch (own mass) gives bitwise the result it gets alone."""
+    dims = (8, 8, 4, 4)
+    U = li.near_unity_gauge(dims, 77, 0.3)
+    bs = li.gaussian_spinors(dims, [78, 79, 80])
+    masses = [0.05, 0.2, 0.5]
+    for inner in (w.WD_FP64, w.WD_FP32):
+        rc, xs, stats, _ = solve(U, masses, bs, inner)
+        assert rc == w.WD_OK, stats
+        for k in range(3):
+            rc1, x1, st1, _ = solve(U, [masses[k]], bs[k][None], inner)
+            assert rc1 == w.WD_OK
+            assert np.array_equal(x1[0], xs[k])
+            assert st1[0]["iters"] == stats[k]["iters"]
+            assert true_rel_residual(U, masses[k], bs[k], xs[k]) <= 1e-10
+        # heavier masses converge in fewer iterations
+        assert stats[2]["iters"] < stats[0]["iters"]
+
+
+def test_cg_start_from_solution_and_zero_rhs():
+    dims = (4, 4, 4, 4)
+    U = li.near_unity_gauge(dims, 5, 0.3)
+    b = li.gaussian_spinor(dims, 6)
+    m = 0.1
+    rc, xs, stats, _ = solve(U, [m], b[None], w.WD_FP64)
+    assert rc == w.WD_OK
+    rc2, xs2, stats2, _ = solve(U, [m], b[None], w.WD_FP64, x0=xs[0])
+    assert rc2 == w.WD_OK and stats2[0]["iters"] == 0
+    assert np.array_equal(xs2[0], xs[0])
+    rc3, xs3, stats3, _ = solve(U, [m], np.zeros_like(b)[None], w.WD_FP32)
+    assert rc3 == w.WD_OK and stats3[0]["iters"] == 0 and not np.any(xs3[0])
+
+
+def test_cg_not_converged_and_numeric():
+    dims = (4, 4, 4, 4)
+    U = li.near_unity_gauge(dims, 5, 0.3)
+    b = li.gaussian_spinor(dims, 6)
+    rc, xs, stats, _ = solve(U, [0.05], b[None], w.WD_FP64, max_iter=3)
+    assert rc == w.WD_ERR_NOT_CONVERGED and stats[0]["status"] == w.WD_ERR_NOT_CONVERGED
+    assert stats[0]["iters"] == 3 and stats[0]["true_rel_residual"] > 1e-10
+    # the reported true residual is the oracle's
+    assert abs(stats[0]["true_rel_residual"] - true_rel_residual(U, 0.05, b, xs[0])) <= 1e-12
+    bad = b.copy()
+    bad[0, 0, 0, 0, 0, 0] = np.nan
+    rc, _, stats, _ = solve(U, [0.05], bad[None], w.WD_FP32)
+    assert rc == w.WD_ERR_NUMERIC and stats[0]["status"] == w.WD_ERR_NUMERIC
+
+
+def test_cg_argument_errors():
+    dims = (4, 4, 4, 4)
+    U = li.near_unity_gauge(dims, 5, 0.3)
+    ghi = DeviceGauge(U, w.WD_FP64)
+    glo = DeviceGauge(U, w.WD_FP32)
+    b = ghi.spinor(1)
+    x = ghi.spinor(1)
+    ws = torch.empty(w.cg_workspace_bytes(dims, 1, w.WD_FP32), dtype=torch.uint8, device="cuda")
+    good = dict(tol=1e-10, max_iter=100, inner=w.WD_FP32, delta=0.1, check_every=1, x0_given=0)
+
+    def code(**kw):
+        args = dict(g_hi=ghi.handle, g_lo=glo.handle, masses=[0.1], nrhs=1, b=b, x=x, params=good,
+                    ws=ws)
+        args.update(kw)
+        with pytest.raises(w.WilsonError) as e:
+            w.cg_solve_normal(args["g_hi"], args["g_lo"], args["masses"], args["nrhs"], args["b"],
+                              args["x"], args["params"], args["ws"], ws_bytes=kw.get("ws_bytes"))
+        return e.value.code
+
+    assert code(nrhs=0, masses=[]) == w.WD_ERR_UNSUPPORTED
+    assert code(nrhs=17, masses=[0.1] * 17) == w.WD_ERR_UNSUPPORTED
+    assert code(params=dict(good, tol=0.0)) == w.WD_ERR_INVALID_ARG
+    assert code(params=dict(good, delta=1.5)) == w.WD_ERR_INVALID_ARG
+    assert code(params=dict(good, inner=w.WD_FP16)) == w.WD_ERR_UNSUPPORTED
+    assert code(g_lo=None) == w.WD_ERR_INVALID_ARG
+    assert code(g_lo=ghi.handle) == w.WD_ERR_INVALID_ARG
+    assert code(g_hi=glo.handle) == w.WD_ERR_INVALID_ARG
+    assert code(ws_bytes=ws.numel() - 1) == w.WD_ERR_INVALID_ARG
+    assert code(x=b) == w.WD_ERR_INVALID_ARG
+    assert code(masses=[float("inf")]) == w.WD_ERR_INVALID_ARG
+    assert w.cg_workspace_bytes(dims, 0, w.WD_FP64) == 0
