@@ -65,6 +65,8 @@ def parse(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the secondary precision/compression measurements")
+    ap.add_argument("--no-multi", action="store_true", help="skip the multi-RHS measurement")
+    ap.add_argument("--no-cg", action="store_true", help="skip the CG solves/s measurement")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain device copy of known size (PMC calibration)")
     return ap.parse_args(argv)
@@ -99,6 +101,71 @@ def time_applies(torch, w, g, src, dst, mass, steps, warmup):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps  # ms per apply
+
+
+def bench_multi(torch, w, li, DeviceGauge, steps=50, warmup=5):
+    """12 right-hand sides on 24^3 x 48, near-unity links, FP32: one fused launch
+    against 12 single launches."""
+    dims, nrhs = (24, 24, 24, 48), 12
+    V = li.volume(dims)
+    U = li.near_unity_gauge(dims, li.seed_gauge(3), 0.3)
+    psis = li.gaussian_spinors(dims, [li.seed_spinor(3, k) for k in range(nrhs)])
+    masses = [0.1] * nrhs
+    g = DeviceGauge(U, w.WD_FP32)
+    src = g.pack(psis, nrhs=nrhs)
+    dst = g.spinor(nrhs)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    fused = timed(lambda: w.dslash_apply_multi(g.handle, masses, nrhs, src, dst, g.prec))
+    one = g.spinor(1)
+    res = g.spinor(1)
+    single = timed(lambda: w.dslash_apply(g.handle, 0.1, one, res, g.prec)) * nrhs
+    comp = 4 * (4 * 18 + nrhs * 48)  # FP32 bytes/site: links once + 12 x (in + out)
+    return {"workload": "wilson_dslash_multi_24x24x24x48_x12", "prec": "fp32", "links": "full",
+            "gauge": "near-unity eps=0.3", "ms_per_apply": round(fused, 4),
+            "gflops": round(nrhs * FLOPS_PER_SITE * V / (fused / 1e3) / 1e9, 1),
+            "pct_hbm_peak": round(100 * comp * V / (fused / 1e3) / 1e9 / HBM_PEAK_GBS, 2),
+            "ms_12_single_applies": round(single, 4), "speedup_vs_single": round(single / fused, 3)}
+
+
+def bench_cg(torch, w, li, DeviceGauge, reps=3):
+    """Solves of D^dag D x = b on 24^4, m = 0.05, near-unity links, to a true
+    residual of 1e-10: plain FP64 CG against FP32 inner + FP64 reliable updates."""
+    dims, m = (24, 24, 24, 24), 0.05
+    U = li.near_unity_gauge(dims, li.seed_gauge(4), 0.3)
+    b = li.gaussian_spinor(dims, li.seed_spinor(4))
+    ghi = DeviceGauge(U, w.WD_FP64)
+    glo = DeviceGauge(U, w.WD_FP32)
+    bd = ghi.pack(b)
+    x = ghi.spinor(1)
+    out = {"workload": "cg_normal_24x24x24x24_m0.05", "tol": 1e-10, "gauge": "near-unity eps=0.3"}
+    for name, inner in (("fp64", w.WD_FP64), ("mixed_fp32", w.WD_FP32)):
+        ws = torch.empty(w.cg_workspace_bytes(dims, 1, inner), dtype=torch.uint8, device="cuda")
+        params = dict(tol=1e-10, max_iter=20000, inner=inner, delta=0.1, check_every=8, x0_given=0)
+        w.cg_solve_normal(ghi.handle, glo.handle, [m], 1, bd, x, params, ws)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rc, st = w.cg_solve_normal(ghi.handle, glo.handle, [m], 1, bd, x, params, ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"status": rc, "solves_per_s": round(1.0 / dt, 2), "ms_per_solve": round(dt * 1e3, 2),
+                     "iters": st[0]["iters"], "reliable_updates": st[0]["reliable_updates"],
+                     "true_rel_residual": st[0]["true_rel_residual"]}
+        del ws
+    out["mixed_speedup"] = round(out["fp64"]["ms_per_solve"] / out["mixed_fp32"]["ms_per_solve"], 3)
+    return out
 
 
 def main(argv=None):
@@ -179,6 +246,15 @@ def main(argv=None):
                                       / HBM_PEAK_GBS, 2)}
             del gv, sv, dv
     copy_gbs = copy_calibration(torch)
+    del Ud, psid
+    multi = None
+    if not args.no_multi:
+        print("[bench] multi-RHS 24^3x48 x12", file=sys.stderr, flush=True)
+        multi = bench_multi(torch, w, li, DeviceGauge)
+    cg = None
+    if not args.no_cg:
+        print("[bench] CG 24^4", file=sys.stderr, flush=True)
+        cg = bench_cg(torch, w, li, DeviceGauge)
 
     workload = "wilson_dslash_" + "x".join(map(str, dims))
     key = f"{workload}_{args.prec}{'_c12' if args.c12 else ''}"
@@ -223,6 +299,8 @@ def main(argv=None):
         "pack_ms": round(pack_ms, 4),
         "torch_copy_gbs": round(copy_gbs, 1),
         "variants": variants,
+        "multi_rhs": multi,
+        "cg": cg,
         "kernel_source_sha": kernel_source_hash(),
         "cpu_baseline": cpu,
     }

@@ -35,9 +35,12 @@
  *             faults inside a kernel surface at the next synchronising call.
  *             wd_last_error() describes the last failure of this thread.
  *             Device pointers are checked with the HIP runtime: a host
- *             pointer, a pointer on another device, or a buffer that ends
- *             before the bytes the call needs is rejected with
- *             WD_ERR_INVALID_ARG. No C++ exception crosses this interface.
+ *             pointer, a pointer on another device, or a buffer whose HIP
+ *             allocation ends before the bytes the call needs is rejected
+ *             with WD_ERR_INVALID_ARG. (A sub-allocation of a caching
+ *             allocator, e.g. a torch tensor, is checked against the segment
+ *             that holds it; sizing it is the caller's job.) No C++
+ *             exception crosses this interface.
  */
 #ifndef WILSON_H
 #define WILSON_H
@@ -139,6 +142,19 @@ WD_API int wd_spinor_export(const wd_gauge* g, const void* src_dev, int32_t prec
 WD_API int dslash_apply(const wd_gauge* g, double mass, const void* in_dev, void* out_dev,
                  int32_t prec, int32_t flags, hipStream_t stream);
 
+/* out_k = D(masses_host[k]) in_k for k < nrhs (0..16; 0 is a no-op) in one
+ * fused launch: the nrhs fields are consecutive packed spinors of precision
+ * prec in in_dev and out_dev (wd_spinor_bytes(dims, prec, nrhs) bytes each;
+ * eq. (1) of Sec. II-A per right-hand side, flags as for dslash_apply).
+ * Each gauge link is fetched from HBM once per launch and served from L2 to
+ * the other right-hand sides. Results equal nrhs separate dslash_apply calls
+ * bit for bit. Asynchronous on stream.
+ * Errors: WD_ERR_INVALID_ARG (buffers, masses, precision, flags),
+ * WD_ERR_UNSUPPORTED (nrhs > 16), WD_ERR_DEVICE (launch). */
+WD_API int dslash_apply_multi(const wd_gauge* g, const double* masses_host, int32_t nrhs,
+                              const void* in_dev, void* out_dev, int32_t prec, int32_t flags,
+                              hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Conjugate gradient on the normal equations D^dag D x = b.
  *
@@ -193,6 +209,90 @@ WD_API int cg_solve_normal(const wd_gauge* g_hi, const wd_gauge* g_lo, const dou
                            int32_t nrhs, const void* b_dev, void* x_dev,
                            const wd_cg_params* params, wd_cg_stats* stats_host, void* ws_dev,
                            size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Request server: continuous batching of CG solves (cg_solve_normal's
+ * algorithm) on gauge fields kept resident in a caller-given arena.
+ *
+ * A scheduler thread groups the right-hand sides of requests on the same
+ * gauge field into slots that iterate together (one fused multi-right-hand-
+ * side dslash per operator application). Requests join a group at chunk
+ * boundaries (check_every iterations) as slots and arena memory free up, and
+ * leave it when converged; groups of different lattices run on separate
+ * streams and overlap on the device. A right-hand side gets bit-identical
+ * results alone or in any mix. Requests wait (first fit in arrival order,
+ * with a bound on how often one can be passed over) until a group of their
+ * gauge field has free slots or the arena has room for a new group.
+ * All server calls are thread-safe.
+ * ------------------------------------------------------------------------ */
+
+typedef struct wd_server wd_server; /* opaque */
+
+typedef struct wd_server_cfg {
+  void* arena_dev;            /* caller-owned device memory; the server owns it until destroyed */
+  size_t arena_bytes;
+  int32_t inner;              /* WD_FP32 (mixed precision) or WD_FP64 */
+  int32_t check_every;        /* >= 1: CG iterations per chunk */
+  double delta;               /* reliable-update threshold (WD_FP32), in (0, 1) */
+  int32_t max_rhs_per_group;  /* 1..16 slots per group; also the largest nrhs of a request */
+  int32_t n_streams;          /* 1..16 streams the groups are spread over */
+} wd_server_cfg;
+
+typedef struct wd_request {
+  uint64_t gauge_id;    /* from wd_server_add_gauge */
+  int32_t nrhs;         /* 1..max_rhs_per_group */
+  int32_t max_iter;     /* >= 1 */
+  double tol;           /* > 0: |b - D^dag D x| <= tol |b| per right-hand side */
+  double masses[16];    /* masses[k] for k < nrhs */
+  const void* b_dev;    /* nrhs packed FP64 spinors of the gauge field's lattice */
+  void* x_dev;          /* nrhs packed FP64 spinors, written when the request completes */
+} wd_request;
+
+typedef struct wd_result {
+  int32_t status;                       /* WD_PENDING, WD_OK, WD_ERR_NOT_CONVERGED, WD_ERR_NUMERIC, WD_ERR_CANCELLED */
+  int32_t nrhs;
+  double t_submit, t_start, t_done;     /* seconds since the server was created (-1: not yet) */
+  wd_cg_stats stats[16];                /* per right-hand side; seconds = time since admission */
+} wd_result;
+
+typedef struct wd_server_state {
+  size_t arena_in_use;   /* bytes of the arena allocated now */
+  size_t arena_peak;     /* most bytes allocated at once so far */
+  int32_t unfinished;    /* submitted requests not yet complete */
+  int32_t gauges;        /* registered gauge fields */
+} wd_server_state;
+
+/* Creates a server on the current device with its scheduler thread. The
+ * arena must stay valid until wd_server_destroy returns. */
+WD_API int wd_server_create(const wd_server_cfg* cfg, wd_server** out);
+
+/* Packs the canonical complex128 gauge field U_canon_dev (FP64, plus FP32 for
+ * mixed precision) into the arena and returns its id; U_canon_dev is not
+ * kept. Synchronous. WD_ERR_NOMEM if the arena has no room. */
+WD_API int wd_server_add_gauge(wd_server* s, const int32_t dims[4], const void* U_canon_dev,
+                               uint64_t* gauge_id);
+
+/* The gauge field takes no new requests; its memory returns to the arena
+ * once its queued and running requests are done. */
+WD_API int wd_server_remove_gauge(wd_server* s, uint64_t gauge_id);
+
+/* Queues a solve and returns at once with a ticket. b_dev and x_dev are
+ * caller-owned and must stay valid until cg_poll reports a final status
+ * (b_dev is copied into the arena when the request is admitted). */
+WD_API int cg_submit(wd_server* s, const wd_request* req, uint64_t* ticket);
+
+/* WD_PENDING while the request is queued or running (out, if non-NULL, gets
+ * the times so far); otherwise its final status, once: the ticket is then
+ * forgotten (a later poll returns WD_ERR_UNKNOWN_TICKET). */
+WD_API int cg_poll(wd_server* s, uint64_t ticket, wd_result* out);
+
+/* Arena use and queue state (for footprint checks and monitoring). */
+WD_API int wd_server_info(wd_server* s, wd_server_state* out);
+
+/* Cancels queued and running requests (WD_ERR_CANCELLED, x not written),
+ * waits for the device work in flight, joins the scheduler and frees the
+ * server (not the arena). NULL is a no-op. */
+WD_API int wd_server_destroy(wd_server* s);
 
 #ifdef __cplusplus
 } /* extern "C" */

@@ -1,6 +1,7 @@
 // C entry points of wilson.h: argument checks, handles, dispatch to kernels.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -254,6 +255,36 @@ int dslash_apply(const wd_gauge* g, double mass, const void* in_dev, void* out_d
     return launch_status(launch_dslash(g, mass, in_dev, out_dev, flags, stream), "dslash");
   } catch (...) {
     return set_error(WD_ERR_INTERNAL, "unexpected exception in dslash_apply");
+  }
+}
+
+int dslash_apply_multi(const wd_gauge* g, const double* masses_host, int32_t nrhs,
+                       const void* in_dev, void* out_dev, int32_t prec, int32_t flags,
+                       hipStream_t stream) {
+  try {
+    clear_error();
+    int rc = check_gauge(g);
+    if (rc != WD_OK) return rc;
+    if ((rc = check_prec(prec)) != WD_OK) return rc;
+    if (prec != g->prec)
+      return set_error(WD_ERR_INVALID_ARG, "spinor precision %d differs from the gauge field's %d",
+                       prec, g->prec);
+    if (flags & ~WD_FLAG_GAMMA5) return set_error(WD_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (nrhs < 0) return set_error(WD_ERR_INVALID_ARG, "nrhs is %d", nrhs);
+    if (nrhs > kMaxMultiRhs)
+      return set_error(WD_ERR_UNSUPPORTED, "nrhs %d exceeds %d per launch", nrhs, kMaxMultiRhs);
+    if (nrhs == 0) return WD_OK;
+    if (masses_host == nullptr) return set_error(WD_ERR_INVALID_ARG, "masses_host is NULL");
+    for (int k = 0; k < nrhs; ++k)
+      if (!std::isfinite(masses_host[k])) return set_error(WD_ERR_INVALID_ARG, "mass %d is not finite", k);
+    const size_t n = static_cast<size_t>(packed_sites(g->V)) * nrhs * spinor_site_bytes(prec);
+    if ((rc = check_device_range(in_dev, n, "in_dev")) != WD_OK) return rc;
+    if ((rc = check_device_range(out_dev, n, "out_dev")) != WD_OK) return rc;
+    if (overlaps(in_dev, n, out_dev, n)) return set_error(WD_ERR_INVALID_ARG, "in_dev and out_dev overlap");
+    return launch_status(launch_dslash_multi(g, masses_host, nrhs, nullptr, in_dev, out_dev, flags,
+                                             stream), "dslash_multi");
+  } catch (...) {
+    return set_error(WD_ERR_INTERNAL, "unexpected exception in dslash_apply_multi");
   }
 }
 

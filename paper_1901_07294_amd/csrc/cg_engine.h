@@ -1,0 +1,69 @@
+// Enqueue-only building blocks of the CG solver, shared by the synchronous
+// cg_solve_normal and the request server (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "blas.h"
+#include "wd_internal.h"
+
+namespace wd {
+
+// Offsets (bytes) of a CG workspace for `slots` right-hand sides.
+struct CgLayout {
+  size_t bytes = 0;
+  size_t r_hi = 0, t_hi = 0, r = 0, p = 0, t = 0, ap = 0, partials = 0, scal = 0;
+};
+CgLayout cg_layout(long V, int slots, int inner);
+
+size_t align256(size_t b);
+
+// What the host does with a right-hand side after reading its scalars.
+enum CgAction { kCgContinue, kCgRefresh, kCgNumeric };
+// ... and after its true residual was recomputed.
+enum CgOutcome { kCgKeepGoing, kCgConverged, kCgNotConverged, kCgFailed };
+
+// sc: the kScalars doubles of one right-hand side.
+CgAction cg_check(const double* sc, double tol, bool mixed, double delta, bool at_max);
+CgOutcome cg_after_refresh(const double* sc, double tol, bool at_max);
+
+// CG on D^dag D for up to kMaxRhs slots that share one lattice and gauge
+// field. Slot k's vectors are field k of each buffer: b and x (FP64 packed,
+// caller- or server-owned) and the workspace. Every method only enqueues
+// work on the stream and returns a wd_status.
+class CgEngine {
+ public:
+  CgEngine(const wd_gauge* ghi, const wd_gauge* glo, int inner, int slots, const void* b, void* x,
+           void* ws, hipStream_t st);
+
+  void set_mass(int slot, double m) { masses_[slot] = m; }
+  int inner() const { return inner_; }
+
+  // scalars of the slots zeroed, <b,b>, x = 0 and r = b (or r = b - A x
+  // when x0_given), inner residual and p = r.
+  int start(const RhsSet& set, bool x0_given);
+  // one CG iteration on the slots of set
+  int iterate(const RhsSet& set);
+  // FP64 true residual r = b - A x; inner residual restarted from it
+  int refresh(const RhsSet& set);
+  // copies the scalars of every slot to host memory (async; pinned memory
+  // for a true overlap)
+  int fetch_scalars(double* host) const;
+
+ private:
+  const wd_gauge* ghi_;
+  const wd_gauge* glo_;
+  int inner_;
+  int slots_;
+  const void* b_;
+  void* x_;
+  void* ws_;
+  hipStream_t st_;
+  long V_ = 0, nhi_ = 0, nlo_ = 0;
+  CgLayout lay_;
+  double* partials_ = nullptr;
+  double* scal_ = nullptr;
+  double masses_[kMaxRhs] = {};
+};
+
+}  // namespace wd

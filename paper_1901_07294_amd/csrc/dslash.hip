@@ -18,6 +18,9 @@
 #ifndef WD_DSLASH_BLOCK
 #define WD_DSLASH_BLOCK 256   // threads per workgroup
 #endif
+#ifndef WD_MARCH_GW
+#define WD_MARCH_GW 0         // right-hand sides per t-marching workgroup; 0 picks automatically
+#endif
 #ifndef WD_XCD_GROUP
 #define WD_XCD_GROUP -1       // tiles per XCD run; -1 picks automatically
 #endif
@@ -28,21 +31,18 @@
 #define WD_MARCH_THREADS 256  // target sites per t-marching tile
 #endif
 #ifndef WD_MARCH_WG_PER_CU
-#define WD_MARCH_WG_PER_CU 2  // t-marching workgroups per CU aimed for (LDS permitting)
-#endif
-#ifndef WD_MARCH_XCD_GROUP
-#define WD_MARCH_XCD_GROUP 32 // preferred XCD run length of t-marching tiles
+#define WD_MARCH_WG_PER_CU 4  // t-marching workgroups per CU aimed for (LDS permitting)
 #endif
 
 namespace wd {
 namespace {
 
 constexpr int kDslashBlock = WD_DSLASH_BLOCK;
-constexpr int kMarchMaxThreads = 256;
+constexpr int kMarchMaxThreads = 256;       // lanes of a one-right-hand-side tile
+constexpr int kMarchMultiThreads = 768;     // lanes of a several-right-hand-side workgroup
 constexpr int kMarchTargetThreads = WD_MARCH_THREADS;
 constexpr int kMarchWgPerCu = WD_MARCH_WG_PER_CU;
 constexpr int kNumCu = 256;
-constexpr int kMarchXcdGroup = WD_MARCH_XCD_GROUP;
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 
 // Workgroup -> tile of kBlock consecutive sites. Consecutive workgroups are
@@ -59,13 +59,18 @@ __device__ __forceinline__ int tile_of_block(int group) {
 }
 
 template <typename R, bool C12>
-__global__ __launch_bounds__(kDslashBlock) void dslash_kernel(const typename Packed<R>::S* __restrict__ in,
-                                                        typename Packed<R>::S* __restrict__ out,
+__global__ __launch_bounds__(kDslashBlock) void dslash_kernel(const typename Packed<R>::S* __restrict__ in_all,
+                                                        typename Packed<R>::S* __restrict__ out_all,
                                                         const typename Packed<R>::L* __restrict__ links,
-                                                        Geo geo, R diag, int gamma5, int group) {
+                                                        Geo geo, Diag<R> diags, long stride, int gamma5,
+                                                        int group) {
   const int s = tile_of_block(group) * kDslashBlock + static_cast<int>(threadIdx.x);
   if (s >= geo.V) return;
   const long V = geo.V;
+  const int rhs = blockIdx.y;
+  const typename Packed<R>::S* in = in_all + diags.idx[rhs] * stride;
+  typename Packed<R>::S* out = out_all + diags.idx[rhs] * stride;
+  const R diag = diags.d[rhs];
 
   const int x = s % geo.X;
   const int y = (s / geo.X) % geo.Y;
@@ -119,7 +124,9 @@ struct MarchParams {
   int ny;      // rows per tile (divides Y)
   int tb;      // t steps per workgroup
   int ytiles;  // Y / ny
-  int group;   // XCD run length (tiles), 0 = hardware order
+  int group;   // XCD run length (workgroups), 0 = hardware order
+  int nrhs;    // right-hand sides of the launch
+  int gw;      // right-hand sides per workgroup (divides nrhs)
 };
 
 // Hops of time t that involve sites outside the tile: z forward and
@@ -135,21 +142,35 @@ __device__ __forceinline__ void outer_hops(const typename Packed<R>::S* __restri
   if (y_bwd_out) hop<1, +1, C12, R>(in, links, V, st + dym, st + dym, acc);
 }
 
-template <typename R, bool C12>
-__global__ __launch_bounds__(kMarchMaxThreads) void dslash_march_kernel(
+// MAXT: launch bound; a workgroup holds p.gw right-hand sides of one tile,
+// one group of n = X * ny lanes (and its own two LDS slices) each.
+template <typename R, bool C12, int MAXT>
+__global__ __launch_bounds__(MAXT) void dslash_march_kernel(
     const typename Packed<R>::S* __restrict__ in, typename Packed<R>::S* __restrict__ out,
-    const typename Packed<R>::L* __restrict__ links, Geo geo, R diag, int gamma5, MarchParams p) {
+    const typename Packed<R>::L* __restrict__ links, Geo geo, Diag<R> diags, long stride,
+    int gamma5, MarchParams p) {
   using SV = typename Packed<R>::S;
+  constexpr int kPlanes = sizeof(R) == 8 ? 12 : 6;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int n = geo.X * p.ny;  // sites per tile == threads per workgroup
-  SV* buf0 = reinterpret_cast<SV*>(smem);
-  SV* buf1 = buf0 + (sizeof(R) == 8 ? 12 : 6) * n;
+  const int n = geo.X * p.ny;  // sites per tile == lanes per right-hand side
+  const int slot = static_cast<int>(threadIdx.x) / n;
+  SV* buf0 = reinterpret_cast<SV*>(smem) + slot * 2 * kPlanes * n;
+  SV* buf1 = buf0 + kPlanes * n;
   const long V = geo.V;
 
-  const int tid = static_cast<int>(threadIdx.x);
+  const int tid = static_cast<int>(threadIdx.x) - slot * n;
   const int xl = tid % geo.X;
   const int yl = tid / geo.X;
-  const int b = tile_of_block(p.group);
+  // The p.gw right-hand sides of a workgroup march in lock step (one barrier
+  // per step), so a link line fetched for one of them is an L1/L2 hit for
+  // the others. Further groups of the same tile are consecutive workgroups.
+  const int groups = p.nrhs / p.gw;
+  const int bb = tile_of_block(p.group);
+  const int rhs = (bb % groups) * p.gw + slot;
+  const int b = bb / groups;
+  in += diags.idx[rhs] * stride;
+  out += diags.idx[rhs] * stride;
+  const R diag = diags.d[rhs];
   const int yt = b % p.ytiles;
   const int z = (b / p.ytiles) % geo.Z;
   const int tblk = b / (p.ytiles * geo.Z);
@@ -177,12 +198,13 @@ __global__ __launch_bounds__(kMarchMaxThreads) void dslash_march_kernel(
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
 
-  // prologue: the carried hops of t0 and the first slice in LDS
+  // prologue: the carried hops of t0 (in the loop's order: outer hops, then
+  // the backward t hop, so every site rounds alike) and the first slice in LDS
   {
     const int tm = t0 == 0 ? geo.T - 1 : t0 - 1;
-    hop<3, +1, C12, R>(in, links, V, s0 + tm * geo.XYZ, s0 + tm * geo.XYZ, acc);
     const int st = s0 + t0 * geo.XYZ;
     outer_hops<C12, R>(in, links, V, st, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, acc);
+    hop<3, +1, C12, R>(in, links, V, s0 + tm * geo.XYZ, s0 + tm * geo.XYZ, acc);
     cx<R> psi[12];
     load_spinor(in, V, st, psi);
     lds_store_spinor(buf0, n, tid, psi);
@@ -252,6 +274,8 @@ __global__ __launch_bounds__(kMarchMaxThreads) void dslash_march_kernel(
   }
 }
 
+// Run length of consecutive workgroups per XCD: the largest power of two up
+// to `preferred` that divides the grid evenly.
 int xcd_group(int nblocks, int preferred) {
   if (WD_XCD_GROUP >= 0) return WD_XCD_GROUP;
   for (int g = preferred; g > 1; g /= 2)
@@ -267,8 +291,8 @@ size_t march_lds_bytes(int threads, size_t real_bytes) {
 
 
 
-MarchParams march_params(const Geo& geo, size_t real_bytes) {
-  MarchParams p{0, 0, 0, 0};
+MarchParams march_params(const Geo& geo, size_t real_bytes, int nrhs) {
+  MarchParams p{0, 0, 0, 0, nrhs, 1};
   if (geo.X > kMarchMaxThreads) return p;
   int ny = 0;
   for (int d = 1; d <= geo.Y; ++d)
@@ -278,77 +302,124 @@ MarchParams march_params(const Geo& geo, size_t real_bytes) {
   if (ny == 0 || geo.X * ny < 64) return p;
   p.ny = ny;
   p.ytiles = geo.Y / ny;
-  const int planes = p.ytiles * geo.Z;
+  const int n = geo.X * ny;
+  const size_t lds1 = march_lds_bytes(n, real_bytes);
+  // right-hand sides per workgroup (FP32 only: two FP64 tiles exceed the
+  // LDS): a divisor of nrhs that the lanes and LDS of a CU allow, preferring
+  // the largest that still fills every CU in one round
+  const int columns = p.ytiles * geo.Z;
+  if (real_bytes == 4) {
+    int best = 1;
+    for (int gw = 2; gw <= kMaxMultiRhs && gw <= nrhs; ++gw) {
+      if (nrhs % gw != 0 || gw * n > kMarchMultiThreads || gw * lds1 > kLdsBytes) continue;
+      if (WD_MARCH_GW > 0 && gw != WD_MARCH_GW) continue;
+      const int per_cu = static_cast<int>(kLdsBytes / (gw * lds1));
+      const int slots = kNumCu * (per_cu < kMarchWgPerCu ? per_cu : kMarchWgPerCu);
+      const int wgs = columns * (nrhs / gw);
+      if (WD_MARCH_GW > 0 || (wgs <= slots && wgs * 4 >= slots * 3)) best = gw;
+    }
+    p.gw = best;
+  }
+  const int planes = columns * (nrhs / p.gw);
   // as many workgroups as fit on the chip at once (LDS decides how many per
-  // CU), t steps split evenly among the workgroups of one tile column
-  const int per_cu = static_cast<int>(kLdsBytes / march_lds_bytes(geo.X * ny, real_bytes));
-  const int target = kNumCu * (per_cu < kMarchWgPerCu ? per_cu : kMarchWgPerCu);
-  int nt = (target + planes - 1) / planes;
-  nt = nt < 1 ? 1 : (nt > geo.T ? geo.T : nt);
+  // CU), without a second round, and at least 4 t steps per workgroup so the
+  // prologue of each march stays cheap; t steps split evenly
+  const int per_cu = static_cast<int>(kLdsBytes / (p.gw * lds1));
+  const int slots = kNumCu * (per_cu < kMarchWgPerCu ? per_cu : kMarchWgPerCu);
+  int nt = slots / planes;
+  const int nt_max = geo.T / 4 > 1 ? geo.T / 4 : 1;
+  nt = nt < 1 ? 1 : (nt > nt_max ? nt_max : nt);
   p.tb = (geo.T + nt - 1) / nt;
   const int nb = planes * ((geo.T + p.tb - 1) / p.tb);
-  p.group = xcd_group(nb, kMarchXcdGroup);
+  // every XCD gets one contiguous eighth of the workgroups: the right-hand
+  // sides, y tiles and z planes that share links and halo slices meet in one L2
+  p.group = WD_XCD_GROUP >= 0 ? WD_XCD_GROUP : (nb % kNumXcd == 0 ? nb / kNumXcd : 0);
   return p;
 }
 
-template <typename R, bool C12>
-hipError_t launch_march(const void* in, void* out, const void* links, const Geo& geo, R diag,
-                        int g5, const MarchParams& p, hipStream_t st) {
+template <typename R, bool C12, int MAXT>
+hipError_t launch_march_t(const void* in, void* out, const void* links, const Geo& geo,
+                          const Diag<R>& diag, long stride, int g5, const MarchParams& p,
+                          hipStream_t st) {
   using SV = typename Packed<R>::S;
   using LV = typename Packed<R>::L;
-  const int threads = geo.X * p.ny;
-  const size_t lds = march_lds_bytes(threads, sizeof(R));
+  const int n = geo.X * p.ny;
+  const size_t lds = p.gw * march_lds_bytes(n, sizeof(R));
   // raise the kernel's dynamic LDS limit once to the whole LDS of a CU
   static std::atomic<int> attr_set{0};
   if (!attr_set.load(std::memory_order_acquire)) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dslash_march_kernel<R, C12>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(kLdsBytes));
+    hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&dslash_march_kernel<R, C12, MAXT>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
     if (e != hipSuccess) return e;
     attr_set.store(1, std::memory_order_release);
   }
-  const unsigned nb = static_cast<unsigned>(p.ytiles * geo.Z * ((geo.T + p.tb - 1) / p.tb));
-  dslash_march_kernel<R, C12><<<nb, threads, lds, st>>>(
+  const unsigned nb = static_cast<unsigned>((p.nrhs / p.gw) * p.ytiles * geo.Z *
+                                            ((geo.T + p.tb - 1) / p.tb));
+  dslash_march_kernel<R, C12, MAXT><<<nb, p.gw * n, lds, st>>>(
       static_cast<const SV*>(in), static_cast<SV*>(out), static_cast<const LV*>(links), geo, diag,
-      g5, p);
+      stride, g5, p);
   return hipGetLastError();
 }
 
 template <typename R, bool C12>
-hipError_t launch_site(const void* in, void* out, const void* links, const Geo& geo, R diag, int g5,
-                       hipStream_t st) {
+hipError_t launch_march(const void* in, void* out, const void* links, const Geo& geo,
+                        const Diag<R>& diag, long stride, int g5, const MarchParams& p,
+                        hipStream_t st) {
+  if constexpr (sizeof(R) == 4) {
+    if (p.gw > 1)
+      return launch_march_t<R, C12, kMarchMultiThreads>(in, out, links, geo, diag, stride, g5, p,
+                                                        st);
+  }
+  return launch_march_t<R, C12, kMarchMaxThreads>(in, out, links, geo, diag, stride, g5, p, st);
+}
+
+template <typename R, bool C12>
+hipError_t launch_site(const void* in, void* out, const void* links, const Geo& geo,
+                       const Diag<R>& diag, int nrhs, long stride, int g5, hipStream_t st) {
   using SV = typename Packed<R>::S;
   using LV = typename Packed<R>::L;
   const unsigned nb = static_cast<unsigned>((geo.V + kDslashBlock - 1) / kDslashBlock);
   const int group = xcd_group(static_cast<int>(nb), 8);
-  dslash_kernel<R, C12><<<nb, kDslashBlock, 0, st>>>(static_cast<const SV*>(in),
-                                                       static_cast<SV*>(out),
-                                                       static_cast<const LV*>(links), geo, diag,
-                                                       g5, group);
+  dslash_kernel<R, C12><<<dim3(nb, nrhs), kDslashBlock, 0, st>>>(
+      static_cast<const SV*>(in), static_cast<SV*>(out), static_cast<const LV*>(links), geo, diag,
+      stride, g5, group);
   return hipGetLastError();
 }
 
 template <typename R, bool C12>
-hipError_t launch_typed(const void* in, void* out, const void* links, const Geo& geo, double mass,
-                        int g5, hipStream_t st) {
-  const R diag = static_cast<R>(4.0 + mass);
-  const MarchParams p = march_params(geo, sizeof(R));
+hipError_t launch_typed(const void* in, void* out, const void* links, const Geo& geo,
+                        const double* masses, int nrhs, const int* fields, int g5, hipStream_t st) {
+  Diag<R> diag{};
+  for (int k = 0; k < nrhs; ++k) {
+    diag.d[k] = static_cast<R>(4.0 + masses[k]);
+    diag.idx[k] = fields ? fields[k] : k;
+  }
+  const long stride = packed_sites(geo.V) * (sizeof(R) == 8 ? 12 : 6);  // 16-B elements per field
+  const MarchParams p = march_params(geo, sizeof(R), nrhs);
   if (WD_DSLASH_KERNEL == 0 && p.ny > 0)
-    return launch_march<R, C12>(in, out, links, geo, diag, g5, p, st);
-  return launch_site<R, C12>(in, out, links, geo, diag, g5, st);
+    return launch_march<R, C12>(in, out, links, geo, diag, stride, g5, p, st);
+  return launch_site<R, C12>(in, out, links, geo, diag, nrhs, stride, g5, st);
 }
 
 }  // namespace
 
-hipError_t launch_dslash(const wd_gauge* g, double mass, const void* in, void* out, int flags,
-                         hipStream_t st) {
+hipError_t launch_dslash_multi(const wd_gauge* g, const double* masses, int nrhs, const int* fields,
+                               const void* in, void* out, int flags, hipStream_t st) {
+  if (nrhs < 1) return hipSuccess;
+  if (nrhs > kMaxMultiRhs) return hipErrorInvalidValue;
   const Geo geo = make_geo(g->dims);
   const int g5 = (flags & WD_FLAG_GAMMA5) ? 1 : 0;
   if (g->prec == WD_FP64)
-    return g->c12 ? launch_typed<double, true>(in, out, g->links, geo, mass, g5, st)
-                  : launch_typed<double, false>(in, out, g->links, geo, mass, g5, st);
-  return g->c12 ? launch_typed<float, true>(in, out, g->links, geo, mass, g5, st)
-                : launch_typed<float, false>(in, out, g->links, geo, mass, g5, st);
+    return g->c12 ? launch_typed<double, true>(in, out, g->links, geo, masses, nrhs, fields, g5, st)
+                  : launch_typed<double, false>(in, out, g->links, geo, masses, nrhs, fields, g5, st);
+  return g->c12 ? launch_typed<float, true>(in, out, g->links, geo, masses, nrhs, fields, g5, st)
+                : launch_typed<float, false>(in, out, g->links, geo, masses, nrhs, fields, g5, st);
+}
+
+hipError_t launch_dslash(const wd_gauge* g, double mass, const void* in, void* out, int flags,
+                         hipStream_t st) {
+  return launch_dslash_multi(g, &mass, 1, nullptr, in, out, flags, st);
 }
 
 }  // namespace wd

@@ -25,6 +25,15 @@ namespace wd {
 constexpr uint64_t kGaugeMagic = 0x57444741554745ull;  // "WDGAUGE"
 constexpr int kBlock = 256;                           // threads per workgroup, 4 wave64s
 constexpr int kNumXcd = 8;                            // MI355X: 8 XCDs, 32 CUs each
+constexpr int kMaxMultiRhs = 16;                      // right-hand sides per fused launch
+
+// The right-hand sides of a launch (kernel argument): field index in the
+// buffers and diagonal term 4 + m of each.
+template <typename R>
+struct Diag {
+  R d[kMaxMultiRhs];
+  int idx[kMaxMultiRhs];
+};
 
 // Set the thread's last-error text; returns code for `return set_error(...)`.
 int set_error(int code, const char* fmt, ...);
@@ -67,5 +76,9 @@ hipError_t launch_unpack_spinor(const void* src, void* canon, const Geo& geo, in
                                 hipStream_t s);
 hipError_t launch_dslash(const wd_gauge* g, double mass, const void* in, void* out, int flags,
                          hipStream_t s);
+// nrhs (1..kMaxMultiRhs) packed fields of `in` / `out`: field fields[i] (or i
+// if fields is null) with mass masses[i].
+hipError_t launch_dslash_multi(const wd_gauge* g, const double* masses, int nrhs, const int* fields,
+                               const void* in, void* out, int flags, hipStream_t s);
 
 }  // namespace wd

@@ -56,6 +56,34 @@ class wd_cg_stats(ctypes.Structure):
                 "reliable_updates": self.reliable_updates,
                 "true_rel_residual": self.true_rel_residual, "seconds": self.seconds}
 
+class wd_server_cfg(ctypes.Structure):
+    _fields_ = [("arena_dev", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
+                ("inner", ctypes.c_int32), ("check_every", ctypes.c_int32), ("delta", ctypes.c_double),
+                ("max_rhs_per_group", ctypes.c_int32), ("n_streams", ctypes.c_int32)]
+
+
+class wd_request(ctypes.Structure):
+    _fields_ = [("gauge_id", ctypes.c_uint64), ("nrhs", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("masses", ctypes.c_double * 16),
+                ("b_dev", ctypes.c_void_p), ("x_dev", ctypes.c_void_p)]
+
+
+class wd_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("nrhs", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("stats", wd_cg_stats * 16)]
+
+    def as_dict(self):
+        return {"status": self.status, "nrhs": self.nrhs, "t_submit": self.t_submit,
+                "t_start": self.t_start, "t_done": self.t_done,
+                "stats": [self.stats[k].as_dict() for k in range(self.nrhs)]}
+
+
+class wd_server_state(ctypes.Structure):
+    _fields_ = [("arena_in_use", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t),
+                ("unfinished", ctypes.c_int32), ("gauges", ctypes.c_int32)]
+
+
 # Exported C symbols and their ctypes signatures.
 _i32 = ctypes.c_int32
 _vp = ctypes.c_void_p
@@ -71,7 +99,16 @@ SIGNATURES = {
     "wd_spinor_import": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp]),
     "wd_spinor_export": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp]),
     "dslash_apply": (ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp, _i32, _i32, _vp]),
+    "dslash_apply_multi": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp,
+                                          _i32, _i32, _vp]),
     "cg_workspace_bytes": (ctypes.c_size_t, [_dims_t, _i32, _i32]),
+    "wd_server_create": (ctypes.c_int, [ctypes.POINTER(wd_server_cfg), ctypes.POINTER(_vp)]),
+    "wd_server_add_gauge": (ctypes.c_int, [_vp, _dims_t, _vp, ctypes.POINTER(ctypes.c_uint64)]),
+    "wd_server_remove_gauge": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "cg_submit": (ctypes.c_int, [_vp, ctypes.POINTER(wd_request), ctypes.POINTER(ctypes.c_uint64)]),
+    "cg_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(wd_result)]),
+    "wd_server_info": (ctypes.c_int, [_vp, ctypes.POINTER(wd_server_state)]),
+    "wd_server_destroy": (ctypes.c_int, [_vp]),
     "cg_solve_normal": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp,
                                        ctypes.POINTER(wd_cg_params), ctypes.POINTER(wd_cg_stats),
                                        _vp, ctypes.c_size_t, _vp]),
@@ -223,6 +260,12 @@ def dslash_apply(g, mass, inp, out, prec, flags=0, stream=None) -> int:
         _h(g), float(mass), _ptr(inp), _ptr(out), prec, flags, _stream(stream)))
 
 
+def dslash_apply_multi(g, masses, nrhs, inp, out, prec, flags=0, stream=None) -> int:
+    m = (ctypes.c_double * max(1, nrhs))(*[float(v) for v in masses])
+    return _check("dslash_apply_multi", _L().dslash_apply_multi(
+        _h(g), m, nrhs, _ptr(inp), _ptr(out), prec, flags, _stream(stream)))
+
+
 def cg_workspace_bytes(dims, nrhs, inner) -> int:
     return _L().cg_workspace_bytes(_dims(dims), nrhs, inner)
 
@@ -244,3 +287,60 @@ def cg_solve_normal(g_hi, g_lo, masses, nrhs, b, x, params, ws, ws_bytes=None, s
     if check and rc < 0 and rc not in (WD_ERR_NOT_CONVERGED, WD_ERR_NUMERIC):
         raise WilsonError("cg_solve_normal", rc, _L().wd_last_error().decode())
     return rc, [stats[k].as_dict() for k in range(nrhs)]
+
+
+def wd_server_create(arena, inner, check_every=8, delta=0.1, max_rhs_per_group=16, n_streams=4,
+                     arena_bytes=None) -> int:
+    """Returns the server handle (an integer address)."""
+    nb = _nbytes(arena) if arena_bytes is None else int(arena_bytes)
+    cfg = wd_server_cfg(_ptr(arena), nb, inner, check_every, delta, max_rhs_per_group, n_streams)
+    out = ctypes.c_void_p()
+    _check("wd_server_create", _L().wd_server_create(ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def wd_server_add_gauge(server, dims, U_canon) -> int:
+    gid = ctypes.c_uint64()
+    _check("wd_server_add_gauge", _L().wd_server_add_gauge(server, _dims(dims), _ptr(U_canon),
+                                                           ctypes.byref(gid)))
+    return gid.value
+
+
+def wd_server_remove_gauge(server, gauge_id) -> int:
+    return _check("wd_server_remove_gauge", _L().wd_server_remove_gauge(server, gauge_id))
+
+
+def cg_submit(server, gauge_id, masses, b, x, tol=1e-10, max_iter=20000) -> int:
+    """Queues a solve of len(masses) right-hand sides; returns the ticket."""
+    req = wd_request()
+    req.gauge_id = gauge_id
+    req.nrhs = len(masses)
+    req.max_iter = max_iter
+    req.tol = tol
+    for k, m in enumerate(masses):
+        req.masses[k] = float(m)
+    req.b_dev = _ptr(b)
+    req.x_dev = _ptr(x)
+    t = ctypes.c_uint64()
+    _check("cg_submit", _L().cg_submit(server, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def cg_poll(server, ticket):
+    """(status, result dict). WD_PENDING while running; a final status once."""
+    res = wd_result()
+    rc = _L().cg_poll(server, ticket, ctypes.byref(res))
+    if rc in (WD_ERR_UNKNOWN_TICKET, WD_ERR_INVALID_ARG, WD_ERR_DEVICE, WD_ERR_INTERNAL):
+        raise WilsonError("cg_poll", rc, _L().wd_last_error().decode())
+    return rc, res.as_dict()
+
+
+def wd_server_info(server) -> dict:
+    st = wd_server_state()
+    _check("wd_server_info", _L().wd_server_info(server, ctypes.byref(st)))
+    return {"arena_in_use": st.arena_in_use, "arena_peak": st.arena_peak,
+            "unfinished": st.unfinished, "gauges": st.gauges}
+
+
+def wd_server_destroy(server) -> int:
+    return _check("wd_server_destroy", _L().wd_server_destroy(server))
