@@ -67,6 +67,7 @@ def parse(argv=None):
                     help="skip the secondary precision/compression measurements")
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-RHS measurement")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG solves/s measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain device copy of known size (PMC calibration)")
     return ap.parse_args(argv)
@@ -168,6 +169,108 @@ def bench_cg(torch, w, li, DeviceGauge, reps=3):
     return out
 
 
+def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=24, load=0.8, seed=5000):
+    """Request server under a Poisson stream of CG solves (tol 1e-10, FP32
+    inner iterations with FP64 reliable updates) on resident near-unity gauge
+    fields of four lattice sizes; 1..12 right-hand sides per request, masses
+    uniform in [0.05, 0.5]. Capacity is measured with a saturated queue, then
+    latencies at `load` times that rate."""
+    import oracle
+    from paper_1901_07294_amd.buffers import to_device
+    sizes = [(8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 48), (32, 32, 32, 64)]
+    nrhs_max = 12
+    arena = torch.empty(48 << 30, dtype=torch.uint8, device="cuda")
+    srv = w.wd_server_create(arena, w.WD_FP32, check_every=8, delta=0.1,
+                             max_rhs_per_group=nrhs_max, n_streams=4)
+    try:
+        lat = []
+        for i, d in enumerate(sizes):
+            U = li.near_unity_gauge(d, 5100 + i, 0.3)
+            Ud = to_device(U)
+            gid = w.wd_server_add_gauge(srv, d, Ud)
+            packer = DeviceGauge(Ud, w.WD_FP64)
+            del Ud
+            base = [li.gaussian_spinor(d, 5200 + 10 * i + k) for k in range(4)]
+            bs = np.stack([base[k % 4] for k in range(nrhs_max)])
+            pool = packer.pack(bs, nrhs=nrhs_max)   # shared, read-only right-hand sides
+            lat.append({"dims": d, "U": U if i < 2 else None, "gid": gid, "packer": packer,
+                        "pool": pool, "b": bs if i < 2 else None})
+        rng = np.random.default_rng(seed)
+
+        def draw():
+            i = int(rng.integers(0, len(sizes)))
+            nrhs = int(rng.integers(1, nrhs_max + 1))
+            return i, list(rng.uniform(0.05, 0.5, nrhs))
+
+        def submit(i, masses):
+            L = lat[i]
+            x = L["packer"].spinor(len(masses))
+            t = w.cg_submit(srv, L["gid"], masses, L["pool"], x, tol=1e-10)
+            return t, x
+
+        def drain(live, done, deadline):
+            while live:
+                assert time.time() < deadline, "serving measurement timed out"
+                for t in list(live):
+                    rc, res = w.cg_poll(srv, t)
+                    if rc != w.WD_PENDING:
+                        done[t] = (rc, res, live.pop(t))
+                time.sleep(0.0005)
+
+        # capacity: everything queued at once
+        t0 = time.time()
+        live, done = {}, {}
+        for _ in range(n_closed):
+            i, m = draw()
+            t, x = submit(i, m)
+            live[t] = (i, m, x)
+        drain(live, done, t0 + 600)
+        makespan = time.time() - t0
+        capacity = n_closed / makespan
+        # open loop at `load` x capacity
+        lam = load * capacity
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, n_open))
+        live, done = {}, {}
+        t0 = time.time()
+        for a in arrivals:
+            while time.time() - t0 < a:
+                for t in list(live):
+                    rc, res = w.cg_poll(srv, t)
+                    if rc != w.WD_PENDING:
+                        done[t] = (rc, res, live.pop(t))
+                time.sleep(0.0005)
+            i, m = draw()
+            t, x = submit(i, m)
+            live[t] = (i, m, x)
+        drain(live, done, time.time() + 600)
+        wall = time.time() - t0
+        lat_s = np.array([res["t_done"] - res["t_submit"] for rc, res, _ in done.values()])
+        nrhs_total = sum(len(v[2][1]) for v in done.values())
+        ok = sum(rc == w.WD_OK for rc, _, _ in done.values())
+        # oracle check of the small-lattice results
+        worst = 0.0
+        for rc, res, (i, m, x) in done.values():
+            L = lat[i]
+            if L["U"] is None:
+                continue
+            xs = L["packer"].unpack(x, nrhs=len(m))
+            xs = xs if len(m) > 1 else xs[None]
+            for k in range(len(m)):
+                r = L["b"][k] - oracle.normal_op(L["U"], m[k], xs[k])
+                worst = max(worst, float(np.linalg.norm(r) / np.linalg.norm(L["b"][k])))
+        info = w.wd_server_info(srv)
+        return {"workload": "cg_requests_8^4_16^4_24^3x48_32^3x64_poisson", "inner": "fp32+fp64_reliable",
+                "tol": 1e-10, "capacity_req_per_s": round(capacity, 3), "offered_load": load,
+                "requests": n_open, "ok": int(ok), "req_per_s": round(n_open / wall, 3),
+                "rhs_solves_per_s": round(nrhs_total / wall, 2),
+                "p50_ms": round(float(np.percentile(lat_s, 50)) * 1e3, 2),
+                "p99_ms": round(float(np.percentile(lat_s, 99)) * 1e3, 2),
+                "max_true_rel_residual_small_lattices": worst,
+                "arena_peak_gb": round(info["arena_peak"] / 1e9, 2)}
+    finally:
+        w.wd_server_destroy(srv)
+
+
 def main(argv=None):
     args = parse(argv)
     if args.gpus != 1:
@@ -263,6 +366,11 @@ def main(argv=None):
     if rec and rec["source_sha"] == kernel_source_hash():
         traffic = rec["bytes_per_launch"]
 
+    serve = None
+    if not args.no_serve:
+        print("[bench] request server", file=sys.stderr, flush=True)
+        serve = bench_serve(torch, w, li, DeviceGauge)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle (one full application)", file=sys.stderr, flush=True)
@@ -301,6 +409,7 @@ def main(argv=None):
         "variants": variants,
         "multi_rhs": multi,
         "cg": cg,
+        "serve": serve,
         "kernel_source_sha": kernel_source_hash(),
         "cpu_baseline": cpu,
     }

@@ -104,7 +104,10 @@ def random_su3_matrices(rng: np.random.Generator, shape) -> np.ndarray:
 
 def near_unity_su3_matrices(rng: np.random.Generator, shape, eps: float) -> np.ndarray:
     """U = exp(i eps H), H = traceless Hermitian part of a complex Gaussian 3x3."""
-    a = complex_gaussian(rng, tuple(shape) + (3, 3))
+    return _exp_i_eps_h(complex_gaussian(rng, tuple(shape) + (3, 3)), eps)
+
+
+def _exp_i_eps_h(a: np.ndarray, eps: float) -> np.ndarray:
     h = 0.5 * (a + np.conj(np.swapaxes(a, -1, -2)))
     tr = np.trace(h, axis1=-2, axis2=-1).real / 3.0
     h = h - tr[..., None, None] * np.eye(3)
