@@ -79,7 +79,13 @@ typedef enum wd_status {
 
 /* Storage and arithmetic precision of a packed field.
  * WD_FP64: binary64 storage and arithmetic. WD_FP32: binary32 storage and
- * arithmetic. */
+ * arithmetic. WD_FP16: binary16 storage, binary32 arithmetic; a spinor site is
+ * stored as its 24 reals (rounded to binary32) divided by their largest
+ * modulus, which is kept per site as a binary32 scale (52 bytes per site);
+ * links are stored unscaled (entries of an SU(3) matrix are at most 1 in
+ * modulus), each binary64 entry rounded once to binary16. Every rounding is
+ * to nearest even. The paper keeps FP16 for compressing network data
+ * (Sec. V-B); here it is a storage format that halves the bytes of FP32. */
 typedef enum wd_prec { WD_FP64 = 0, WD_FP32 = 1, WD_FP16 = 2 } wd_prec;
 
 /* flags of dslash_apply / dslash_apply_multi */
@@ -110,9 +116,9 @@ WD_API size_t wd_gauge_bytes(const int32_t dims[4], int32_t prec, int32_t compre
  * handle) and returns a handle in *out. The pack is enqueued on stream; the
  * handle may be used at once on the same stream. The canonical buffer is not
  * kept. With compress12 the input links must be SU(3) (unitary, det 1) for
- * the third row to be rebuilt exactly. Precisions: WD_FP64, WD_FP32.
- * Errors: WD_ERR_INVALID_ARG (pointers, out == NULL), WD_ERR_SHAPE (dims),
- * WD_ERR_UNSUPPORTED (precision), WD_ERR_DEVICE (launch). */
+ * the third row to be rebuilt exactly. Precisions: WD_FP64, WD_FP32, WD_FP16.
+ * Errors: WD_ERR_INVALID_ARG (pointers, out == NULL, unknown precision),
+ * WD_ERR_SHAPE (dims), WD_ERR_DEVICE (launch). */
 WD_API int wd_gauge_import(const int32_t dims[4], const void* U_canon_dev, int32_t prec,
                     int32_t compress12, void* dst_dev, size_t dst_bytes,
                     hipStream_t stream, wd_gauge** out);

@@ -30,6 +30,7 @@ size_t spinor_site_bytes(int prec) {
   switch (prec) {
     case WD_FP64: return 24 * sizeof(double);
     case WD_FP32: return 24 * sizeof(float);
+    case WD_FP16: return 24 * 2 + sizeof(float);  // binary16 components + per-site scale
     default: return 0;
   }
 }
@@ -39,6 +40,7 @@ size_t gauge_site_bytes(int prec, int c12) {
   switch (prec) {
     case WD_FP64: return reals * sizeof(double);
     case WD_FP32: return reals * sizeof(float);
+    case WD_FP16: return reals * 2;
     default: return 0;
   }
 }
@@ -61,9 +63,7 @@ int check_dims(const int32_t dims[4], long* V) {
 }
 
 int check_prec(int prec) {
-  if (prec == WD_FP64 || prec == WD_FP32) return WD_OK;
-  if (prec == WD_FP16)
-    return set_error(WD_ERR_UNSUPPORTED, "precision WD_FP16 is not supported by this entry point");
+  if (prec == WD_FP64 || prec == WD_FP32 || prec == WD_FP16) return WD_OK;
   return set_error(WD_ERR_INVALID_ARG, "unknown precision %d", prec);
 }
 

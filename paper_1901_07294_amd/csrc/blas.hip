@@ -35,10 +35,10 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;
 }
 
-__device__ __forceinline__ double norm2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double norm2(double2 a) { return fmar(a.x, a.x, a.y * a.y); }
 __device__ __forceinline__ double norm2(float4 a) {
-  return static_cast<double>(a.x) * a.x + static_cast<double>(a.y) * a.y +
-         static_cast<double>(a.z) * a.z + static_cast<double>(a.w) * a.w;
+  const double x = a.x, y = a.y, z = a.z, w = a.w;
+  return fmar(x, x, fmar(y, y, fmar(z, z, w * w)));
 }
 
 // Is flat element e of a packed field of P elements per site a real site?
@@ -96,11 +96,11 @@ __global__ __launch_bounds__(kThreads) void update_xr_kernel(double2* __restrict
     const T ae = apk[e];
     if constexpr (Elems<T>::P == 12) {
       double2 xe = xk[e];
-      xe.x += alpha * pe.x;
-      xe.y += alpha * pe.y;
+      xe.x = fmar(alpha, pe.x, xe.x);
+      xe.y = fmar(alpha, pe.y, xe.y);
       xk[e] = xe;
-      re.x -= alpha * ae.x;
-      re.y -= alpha * ae.y;
+      re.x = fmar(-alpha, ae.x, re.x);
+      re.y = fmar(-alpha, ae.y, re.y);
     } else {
       // FP32 element j of a block holds FP64 elements 2j and 2j+1 of the same sites
       const long blk = e / (6 * 64);
@@ -109,17 +109,17 @@ __global__ __launch_bounds__(kThreads) void update_xr_kernel(double2* __restrict
       const long h0 = (blk * 12 + 2 * j) * 64 + lane;
       double2 x0 = xk[h0];
       double2 x1 = xk[h0 + 64];
-      x0.x += alpha * pe.x;
-      x0.y += alpha * pe.y;
-      x1.x += alpha * pe.z;
-      x1.y += alpha * pe.w;
+      x0.x = fmar(alpha, static_cast<double>(pe.x), x0.x);
+      x0.y = fmar(alpha, static_cast<double>(pe.y), x0.y);
+      x1.x = fmar(alpha, static_cast<double>(pe.z), x1.x);
+      x1.y = fmar(alpha, static_cast<double>(pe.w), x1.y);
       xk[h0] = x0;
       xk[h0 + 64] = x1;
       const float a = static_cast<float>(alpha);
-      re.x -= a * ae.x;
-      re.y -= a * ae.y;
-      re.z -= a * ae.z;
-      re.w -= a * ae.w;
+      re.x = fmar(-a, ae.x, re.x);
+      re.y = fmar(-a, ae.y, re.y);
+      re.z = fmar(-a, ae.z, re.z);
+      re.w = fmar(-a, ae.w, re.w);
     }
     rk[e] = re;
     if (real_site<Elems<T>::P>(e, V)) s += norm2(re);
@@ -142,14 +142,14 @@ __global__ __launch_bounds__(kThreads) void update_p_kernel(T* __restrict__ p, c
     T pe = pk[e];
     const T re = rk[e];
     if constexpr (Elems<T>::P == 12) {
-      pe.x = re.x + beta * pe.x;
-      pe.y = re.y + beta * pe.y;
+      pe.x = fmar(beta, pe.x, re.x);
+      pe.y = fmar(beta, pe.y, re.y);
     } else {
       const float b = static_cast<float>(beta);
-      pe.x = re.x + b * pe.x;
-      pe.y = re.y + b * pe.y;
-      pe.z = re.z + b * pe.z;
-      pe.w = re.w + b * pe.w;
+      pe.x = fmar(b, pe.x, re.x);
+      pe.y = fmar(b, pe.y, re.y);
+      pe.z = fmar(b, pe.z, re.z);
+      pe.w = fmar(b, pe.w, re.w);
     }
     pk[e] = pe;
   }

@@ -7,12 +7,23 @@
 
 #include <hip/hip_runtime.h>
 
+// Every translation unit that includes this header compiles the code after
+// this point with FMA contraction off: the only fused multiply-adds are the
+// explicit ones below, so a result does not depend on how the compiler
+// schedules the kernel it is computed in (prologue or loop of a march,
+// one or several right-hand sides per workgroup).
+#pragma clang fp contract(off)
+
 namespace wd {
 
 template <typename R>
 struct cx {
   R re, im;
 };
+
+// a * b + c with a single rounding
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 template <typename R>
 __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
@@ -30,20 +41,20 @@ __device__ __forceinline__ cx<R> subi(cx<R> a, cx<R> b) { return {a.re + b.im, a
 // a*b and conj(a)*b
 template <typename R>
 __device__ __forceinline__ cx<R> mul(cx<R> a, cx<R> b) {
-  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+  return {fmar(a.re, b.re, -(a.im * b.im)), fmar(a.re, b.im, a.im * b.re)};
 }
 template <typename R>
 __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
-  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+  return {fmar(a.re, b.re, a.im * b.im), fmar(a.re, b.im, -(a.im * b.re))};
 }
 // c + a*b and c + conj(a)*b
 template <typename R>
 __device__ __forceinline__ cx<R> fma(cx<R> a, cx<R> b, cx<R> c) {
-  return {c.re + a.re * b.re - a.im * b.im, c.im + a.re * b.im + a.im * b.re};
+  return {fmar(-a.im, b.im, fmar(a.re, b.re, c.re)), fmar(a.im, b.re, fmar(a.re, b.im, c.im))};
 }
 template <typename R>
 __device__ __forceinline__ cx<R> cfma(cx<R> a, cx<R> b, cx<R> c) {
-  return {c.re + a.re * b.re + a.im * b.im, c.im + a.re * b.im - a.im * b.re};
+  return {fmar(a.im, b.im, fmar(a.re, b.re, c.re)), fmar(-a.im, b.re, fmar(a.re, b.im, c.im))};
 }
 template <typename R>
 __device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.re, -a.im}; }

@@ -58,18 +58,19 @@ __device__ __forceinline__ int tile_of_block(int group) {
   return ((l / group) * kNumXcd + xcd) * group + (l % group);
 }
 
-template <typename R, bool C12>
-__global__ __launch_bounds__(kDslashBlock) void dslash_kernel(const typename Packed<R>::S* __restrict__ in_all,
-                                                        typename Packed<R>::S* __restrict__ out_all,
-                                                        const typename Packed<R>::L* __restrict__ links,
-                                                        Geo geo, Diag<R> diags, long stride, int gamma5,
-                                                        int group) {
+// T: storage type of spinors and links (double, float or _Float16).
+template <typename T, bool C12>
+__global__ __launch_bounds__(kDslashBlock) void dslash_kernel(
+    const typename Packed<T>::S* __restrict__ in_all, typename Packed<T>::S* __restrict__ out_all,
+    const typename Packed<T>::L* __restrict__ links, Geo geo, Diag<typename Packed<T>::R> diags,
+    long stride, int gamma5, int group) {
+  using R = typename Packed<T>::R;
   const int s = tile_of_block(group) * kDslashBlock + static_cast<int>(threadIdx.x);
   if (s >= geo.V) return;
   const long V = geo.V;
   const int rhs = blockIdx.y;
-  const typename Packed<R>::S* in = in_all + diags.idx[rhs] * stride;
-  typename Packed<R>::S* out = out_all + diags.idx[rhs] * stride;
+  const typename Packed<T>::S* in = in_all + diags.idx[rhs] * stride;
+  typename Packed<T>::S* out = out_all + diags.idx[rhs] * stride;
   const R diag = diags.d[rhs];
 
   const int x = s % geo.X;
@@ -90,14 +91,14 @@ __global__ __launch_bounds__(kDslashBlock) void dslash_kernel(const typename Pac
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
 
-  hop<0, -1, C12, R>(in, links, V, xp, s, acc);
-  hop<0, +1, C12, R>(in, links, V, xm, xm, acc);
-  hop<1, -1, C12, R>(in, links, V, yp, s, acc);
-  hop<1, +1, C12, R>(in, links, V, ym, ym, acc);
-  hop<2, -1, C12, R>(in, links, V, zp, s, acc);
-  hop<2, +1, C12, R>(in, links, V, zm, zm, acc);
-  hop<3, -1, C12, R>(in, links, V, tp, s, acc);
-  hop<3, +1, C12, R>(in, links, V, tm, tm, acc);
+  hop<0, -1, C12>(in, links, V, xp, s, acc);
+  hop<0, +1, C12>(in, links, V, xm, xm, acc);
+  hop<1, -1, C12>(in, links, V, yp, s, acc);
+  hop<1, +1, C12>(in, links, V, ym, ym, acc);
+  hop<2, -1, C12>(in, links, V, zp, s, acc);
+  hop<2, +1, C12>(in, links, V, zm, zm, acc);
+  hop<3, -1, C12>(in, links, V, tp, s, acc);
+  hop<3, +1, C12>(in, links, V, tm, tm, acc);
 
   cx<R> psi[12];
   load_spinor(in, V, s, psi);
@@ -131,24 +132,25 @@ struct MarchParams {
 
 // Hops of time t that involve sites outside the tile: z forward and
 // backward, and the y hops of the tile's edge rows.
-template <bool C12, typename R>
-__device__ __forceinline__ void outer_hops(const typename Packed<R>::S* __restrict__ in,
-                                           const typename Packed<R>::L* __restrict__ links, long V,
-                                           int st, int dzp, int dzm, bool y_fwd_out, int dyp,
+template <bool C12, typename SV, typename LV, typename R>
+__device__ __forceinline__ void outer_hops(const SV* __restrict__ in, const LV* __restrict__ links,
+                                           long V, int st, int dzp, int dzm, bool y_fwd_out, int dyp,
                                            bool y_bwd_out, int dym, cx<R> (&acc)[12]) {
-  hop<2, -1, C12, R>(in, links, V, st + dzp, st, acc);
-  hop<2, +1, C12, R>(in, links, V, st + dzm, st + dzm, acc);
-  if (y_fwd_out) hop<1, -1, C12, R>(in, links, V, st + dyp, st, acc);
-  if (y_bwd_out) hop<1, +1, C12, R>(in, links, V, st + dym, st + dym, acc);
+  hop<2, -1, C12>(in, links, V, st + dzp, st, acc);
+  hop<2, +1, C12>(in, links, V, st + dzm, st + dzm, acc);
+  if (y_fwd_out) hop<1, -1, C12>(in, links, V, st + dyp, st, acc);
+  if (y_bwd_out) hop<1, +1, C12>(in, links, V, st + dym, st + dym, acc);
 }
 
 // MAXT: launch bound; a workgroup holds p.gw right-hand sides of one tile,
-// one group of n = X * ny lanes (and its own two LDS slices) each.
-template <typename R, bool C12, int MAXT>
+// one group of n = X * ny lanes (and its own two LDS slices) each. The LDS
+// slices hold spinors in the arithmetic precision (FP32 for FP16 storage).
+template <typename T, bool C12, int MAXT>
 __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
-    const typename Packed<R>::S* __restrict__ in, typename Packed<R>::S* __restrict__ out,
-    const typename Packed<R>::L* __restrict__ links, Geo geo, Diag<R> diags, long stride,
-    int gamma5, MarchParams p) {
+    const typename Packed<T>::S* __restrict__ in, typename Packed<T>::S* __restrict__ out,
+    const typename Packed<T>::L* __restrict__ links, Geo geo, Diag<typename Packed<T>::R> diags,
+    long stride, int gamma5, MarchParams p) {
+  using R = typename Packed<T>::R;
   using SV = typename Packed<R>::S;
   constexpr int kPlanes = sizeof(R) == 8 ? 12 : 6;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -203,8 +205,8 @@ __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
   {
     const int tm = t0 == 0 ? geo.T - 1 : t0 - 1;
     const int st = s0 + t0 * geo.XYZ;
-    outer_hops<C12, R>(in, links, V, st, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, acc);
-    hop<3, +1, C12, R>(in, links, V, s0 + tm * geo.XYZ, s0 + tm * geo.XYZ, acc);
+    outer_hops<C12>(in, links, V, st, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, acc);
+    hop<3, +1, C12>(in, links, V, s0 + tm * geo.XYZ, s0 + tm * geo.XYZ, acc);
     cx<R> psi[12];
     load_spinor(in, V, st, psi);
     lds_store_spinor(buf0, n, tid, psi);
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
       load_spinor(in, V, sn, psi);
       if (more) {
         lds_store_spinor(nxt, n, tid, psi);
-        outer_hops<C12, R>(in, links, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, nacc);
+        outer_hops<C12>(in, links, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, nacc);
       }
       cx<R> h[6], g[6];
       project<3, -1>(psi, h);
@@ -242,16 +244,16 @@ __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
     {
       cx<R> psi[12];
       lds_load_spinor(cur, n, lxp, psi);
-      hop_psi<0, -1, C12, R>(psi, links, V, st, acc);
+      hop_psi<0, -1, C12>(psi, links, V, st, acc);
       lds_load_spinor(cur, n, lxm, psi);
-      hop_psi<0, +1, C12, R>(psi, links, V, st + dxm, acc);
+      hop_psi<0, +1, C12>(psi, links, V, st + dxm, acc);
       if (!y_fwd_out) {
         lds_load_spinor(cur, n, lyp, psi);
-        hop_psi<1, -1, C12, R>(psi, links, V, st, acc);
+        hop_psi<1, -1, C12>(psi, links, V, st, acc);
       }
       if (!y_bwd_out) {
         lds_load_spinor(cur, n, lym, psi);
-        hop_psi<1, +1, C12, R>(psi, links, V, st + dym, acc);
+        hop_psi<1, +1, C12>(psi, links, V, st + dym, acc);
       }
     }
     // epilogue of t; the backward t hop of t+1 joins the next accumulator
@@ -304,7 +306,7 @@ MarchParams march_params(const Geo& geo, size_t real_bytes, int nrhs) {
   p.ytiles = geo.Y / ny;
   const int n = geo.X * ny;
   const size_t lds1 = march_lds_bytes(n, real_bytes);
-  // right-hand sides per workgroup (FP32 only: two FP64 tiles exceed the
+  // right-hand sides per workgroup (FP32 arithmetic only: two FP64 tiles exceed the
   // LDS): a divisor of nrhs that the lanes and LDS of a CU allow, preferring
   // the largest that still fills every CU in one round
   const int columns = p.ytiles * geo.Z;
@@ -337,69 +339,79 @@ MarchParams march_params(const Geo& geo, size_t real_bytes, int nrhs) {
   return p;
 }
 
-template <typename R, bool C12, int MAXT>
+template <typename T, bool C12, int MAXT>
 hipError_t launch_march_t(const void* in, void* out, const void* links, const Geo& geo,
-                          const Diag<R>& diag, long stride, int g5, const MarchParams& p,
-                          hipStream_t st) {
-  using SV = typename Packed<R>::S;
-  using LV = typename Packed<R>::L;
+                          const Diag<typename Packed<T>::R>& diag, long stride, int g5,
+                          const MarchParams& p, hipStream_t st) {
+  using SV = typename Packed<T>::S;
+  using LV = typename Packed<T>::L;
+  using R = typename Packed<T>::R;
   const int n = geo.X * p.ny;
   const size_t lds = p.gw * march_lds_bytes(n, sizeof(R));
   // raise the kernel's dynamic LDS limit once to the whole LDS of a CU
   static std::atomic<int> attr_set{0};
   if (!attr_set.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&dslash_march_kernel<R, C12, MAXT>),
+        reinterpret_cast<const void*>(&dslash_march_kernel<T, C12, MAXT>),
         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
     if (e != hipSuccess) return e;
     attr_set.store(1, std::memory_order_release);
   }
   const unsigned nb = static_cast<unsigned>((p.nrhs / p.gw) * p.ytiles * geo.Z *
                                             ((geo.T + p.tb - 1) / p.tb));
-  dslash_march_kernel<R, C12, MAXT><<<nb, p.gw * n, lds, st>>>(
+  dslash_march_kernel<T, C12, MAXT><<<nb, p.gw * n, lds, st>>>(
       static_cast<const SV*>(in), static_cast<SV*>(out), static_cast<const LV*>(links), geo, diag,
       stride, g5, p);
   return hipGetLastError();
 }
 
-template <typename R, bool C12>
+template <typename T, bool C12>
 hipError_t launch_march(const void* in, void* out, const void* links, const Geo& geo,
-                        const Diag<R>& diag, long stride, int g5, const MarchParams& p,
-                        hipStream_t st) {
-  if constexpr (sizeof(R) == 4) {
+                        const Diag<typename Packed<T>::R>& diag, long stride, int g5,
+                        const MarchParams& p, hipStream_t st) {
+  if constexpr (sizeof(typename Packed<T>::R) == 4) {
     if (p.gw > 1)
-      return launch_march_t<R, C12, kMarchMultiThreads>(in, out, links, geo, diag, stride, g5, p,
+      return launch_march_t<T, C12, kMarchMultiThreads>(in, out, links, geo, diag, stride, g5, p,
                                                         st);
   }
-  return launch_march_t<R, C12, kMarchMaxThreads>(in, out, links, geo, diag, stride, g5, p, st);
+  return launch_march_t<T, C12, kMarchMaxThreads>(in, out, links, geo, diag, stride, g5, p, st);
 }
 
-template <typename R, bool C12>
+template <typename T, bool C12>
 hipError_t launch_site(const void* in, void* out, const void* links, const Geo& geo,
-                       const Diag<R>& diag, int nrhs, long stride, int g5, hipStream_t st) {
-  using SV = typename Packed<R>::S;
-  using LV = typename Packed<R>::L;
+                       const Diag<typename Packed<T>::R>& diag, int nrhs, long stride, int g5,
+                       hipStream_t st) {
+  using SV = typename Packed<T>::S;
+  using LV = typename Packed<T>::L;
   const unsigned nb = static_cast<unsigned>((geo.V + kDslashBlock - 1) / kDslashBlock);
   const int group = xcd_group(static_cast<int>(nb), 8);
-  dslash_kernel<R, C12><<<dim3(nb, nrhs), kDslashBlock, 0, st>>>(
+  dslash_kernel<T, C12><<<dim3(nb, nrhs), kDslashBlock, 0, st>>>(
       static_cast<const SV*>(in), static_cast<SV*>(out), static_cast<const LV*>(links), geo, diag,
       stride, g5, group);
   return hipGetLastError();
 }
 
-template <typename R, bool C12>
+template <typename T, bool C12>
 hipError_t launch_typed(const void* in, void* out, const void* links, const Geo& geo,
                         const double* masses, int nrhs, const int* fields, int g5, hipStream_t st) {
+  using R = typename Packed<T>::R;
   Diag<R> diag{};
   for (int k = 0; k < nrhs; ++k) {
     diag.d[k] = static_cast<R>(4.0 + masses[k]);
     diag.idx[k] = fields ? fields[k] : k;
   }
-  const long stride = packed_sites(geo.V) * (sizeof(R) == 8 ? 12 : 6);  // 16-B elements per field
+  const long stride = spinor_units<T>(geo.V);  // 16-B elements per field
   const MarchParams p = march_params(geo, sizeof(R), nrhs);
   if (WD_DSLASH_KERNEL == 0 && p.ny > 0)
-    return launch_march<R, C12>(in, out, links, geo, diag, stride, g5, p, st);
-  return launch_site<R, C12>(in, out, links, geo, diag, nrhs, stride, g5, st);
+    return launch_march<T, C12>(in, out, links, geo, diag, stride, g5, p, st);
+  return launch_site<T, C12>(in, out, links, geo, diag, nrhs, stride, g5, st);
+}
+
+template <typename T>
+hipError_t launch_prec(const wd_gauge* g, const void* in, void* out, const Geo& geo,
+                       const double* masses, int nrhs, const int* fields, int g5, hipStream_t st) {
+  return g->c12 ? launch_typed<T, true>(in, out, g->links, geo, masses, nrhs, fields, g5, st)
+                : launch_typed<T, false>(in, out, g->links, geo, masses, nrhs, fields, g5, st);
 }
 
 }  // namespace
@@ -410,11 +422,12 @@ hipError_t launch_dslash_multi(const wd_gauge* g, const double* masses, int nrhs
   if (nrhs > kMaxMultiRhs) return hipErrorInvalidValue;
   const Geo geo = make_geo(g->dims);
   const int g5 = (flags & WD_FLAG_GAMMA5) ? 1 : 0;
-  if (g->prec == WD_FP64)
-    return g->c12 ? launch_typed<double, true>(in, out, g->links, geo, masses, nrhs, fields, g5, st)
-                  : launch_typed<double, false>(in, out, g->links, geo, masses, nrhs, fields, g5, st);
-  return g->c12 ? launch_typed<float, true>(in, out, g->links, geo, masses, nrhs, fields, g5, st)
-                : launch_typed<float, false>(in, out, g->links, geo, masses, nrhs, fields, g5, st);
+  switch (g->prec) {
+    case WD_FP64: return launch_prec<double>(g, in, out, geo, masses, nrhs, fields, g5, st);
+    case WD_FP32: return launch_prec<float>(g, in, out, geo, masses, nrhs, fields, g5, st);
+    case WD_FP16: return launch_prec<_Float16>(g, in, out, geo, masses, nrhs, fields, g5, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_dslash(const wd_gauge* g, double mass, const void* in, void* out, int flags,

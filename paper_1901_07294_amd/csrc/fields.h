@@ -2,62 +2,87 @@
 //
 // Every packed field is an array of structures of arrays: sites are grouped in
 // blocks of 64 consecutive sites (one wave), and inside a block each "plane"
-// (one 8- or 16-byte piece of every site's data) is a contiguous run of 64
-// elements. A wave's load of one plane is one contiguous 512 B - 1 KiB run,
+// (one 4- to 16-byte piece of every site's data) is a contiguous run of 64
+// elements. A wave's load of one plane is one contiguous 256 B - 1 KiB run,
 // and all planes of a block follow each other, so a wave streams its sites'
 // data as one contiguous region (Sec. II-B: the data layout decides how well
 // the stencil vectorises; one lane per site plays the role of Grid's one
 // vector lane per virtual node, without intra-vector permutes).
 //
-//  spinor, per right-hand side (stride packed_sites(V) * 24 reals):
+//  spinor, per right-hand side (blocks of 64 sites, padded):
 //    FP64: 12 planes of double2   plane c = 3*spin + colour
 //    FP32:  6 planes of float4    plane j holds components 2j, 2j+1
+//    FP16:  3 planes of 8 x binary16 (plane j holds components 4j .. 4j+3),
+//           then one plane of FP32 per-site scales: 52 B per site
 //  gauge, all four directions in one block:
 //    FP64 full: 36 planes of double2   plane 9*mu + 3*row + col
 //    FP64 c12 : 24 planes of double2   plane 6*mu + 3*row + col, rows 0-1
 //    FP32 full: 36 planes of float2
 //    FP32 c12 : 12 planes of float4    plane 3*mu + j holds entries 2j, 2j+1 of rows 0-1
+//    FP16 full: 36 planes of 2 x binary16
+//    FP16 c12 : 12 planes of 4 x binary16 (as FP32 c12)
+//
+// FP16 is a storage format only (arithmetic is FP32). A spinor site is stored
+// as q = v / s with s = max |v| over its 24 reals (v in FP32) and read back as
+// float(q) * s; links are stored unscaled (every entry of an SU(3) matrix is at
+// most 1 in modulus), each FP64 entry rounded once to binary16. Every rounding
+// is to nearest even.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include "cplx.h"
 
-// Sites per AoSoA block of a packed field (0: plain planes of V sites).
-#ifndef WD_LAYOUT_BLOCK
-#define WD_LAYOUT_BLOCK 64
-#endif
-
 namespace wd {
 
-constexpr int kLayoutBlock = WD_LAYOUT_BLOCK;
+constexpr int kLayoutBlock = 64;  // sites per AoSoA block of a packed field
 
 // Sites a packed field of V sites is padded to.
 __host__ __device__ constexpr long packed_sites(long V) {
-  return kLayoutBlock > 0 ? (V + kLayoutBlock - 1) / kLayoutBlock * kLayoutBlock : V;
+  return (V + kLayoutBlock - 1) / kLayoutBlock * kLayoutBlock;
 }
 
 // Element index of plane c (of P planes per site) of site s in a packed field.
-__device__ __forceinline__ long pidx(long s, int c, int P, long V) {
-  if constexpr (kLayoutBlock > 0)
-    return ((s / kLayoutBlock) * P + c) * kLayoutBlock + (s % kLayoutBlock);
-  else
-    return c * V + s;
+__device__ __forceinline__ long pidx(long s, int c, int P, long /*V*/) {
+  return ((s / kLayoutBlock) * P + c) * kLayoutBlock + (s % kLayoutBlock);
 }
 
-// Vector types of packed spinors (S) and links (L) per arithmetic precision.
-template <typename R>
+// binary16 vectors of the FP16 storage format.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+// Per storage type T: arithmetic type R, 16-byte spinor element S, link
+// element L, and 16-byte spinor elements per block of 64 sites.
+template <typename T>
 struct Packed;
 template <>
 struct Packed<double> {
+  using R = double;
   using S = double2;
   using L = double2;
+  static constexpr long kBlockUnits = 64 * 12;
 };
 template <>
 struct Packed<float> {
+  using R = float;
   using S = float4;
   using L = float2;
+  static constexpr long kBlockUnits = 64 * 6;
 };
+template <>
+struct Packed<_Float16> {
+  using R = float;
+  using S = h8;
+  using L = h2;
+  static constexpr long kBlockUnits = 64 * 3 + 16;  // 3 planes + 64 FP32 scales
+};
+
+// 16-byte elements of one packed spinor field of V sites.
+template <typename T>
+__host__ __device__ constexpr long spinor_units(long V) {
+  return packed_sites(V) / kLayoutBlock * Packed<T>::kBlockUnits;
+}
 
 // Native vector types for the non-temporal (streaming) stores of results.
 typedef double nd2 __attribute__((ext_vector_type(2)));
@@ -100,6 +125,66 @@ __device__ __forceinline__ void store_spinor(float4* __restrict__ p, long V, int
     const nf4 t = {v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im};
     __builtin_nontemporal_store(t, reinterpret_cast<nf4*>(p + pidx(s, j, 6, V)));
   }
+}
+
+// FP16 spinor: 16-byte element of plane j of site s, and (in floats) the
+// site's scale, which follows the three planes of its block.
+__device__ __forceinline__ long half_unit(long s, int j) {
+  return (s / kLayoutBlock) * Packed<_Float16>::kBlockUnits + j * kLayoutBlock + (s % kLayoutBlock);
+}
+__device__ __forceinline__ long half_scale_index(long s) {
+  return ((s / kLayoutBlock) * Packed<_Float16>::kBlockUnits + 3 * kLayoutBlock) * 4 +
+         (s % kLayoutBlock);
+}
+
+// The product float(q) * scale is rounded on its own (contraction is off),
+// so a site reads the same FP32 values whether they come from here or from a
+// copy staged in LDS.
+__device__ __forceinline__ void load_spinor(const h8* __restrict__ p, long /*V*/, int s,
+                                            cx<float> (&v)[12]) {
+  const float sc = reinterpret_cast<const float*>(p)[half_scale_index(s)];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const h8 t = p[half_unit(s, j)];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      v[4 * j + k] = {static_cast<float>(t[2 * k]) * sc, static_cast<float>(t[2 * k + 1]) * sc};
+  }
+}
+
+// An FP32 value rounded to binary16. The empty asm pins x in a register as
+// an FP32 result, so the compiler cannot merge the multiply that produced it
+// and this conversion into one mixed-precision instruction with a single
+// rounding (which would make the stored bits depend on the kernel).
+__device__ __forceinline__ _Float16 f32_to_half(float x) {
+  __asm__ volatile("" : "+v"(x));
+  return static_cast<_Float16>(x);
+}
+
+// Quantises a site: scale = max |component|, q = v * (1 / scale) rounded to
+// FP32 and then to binary16.
+__device__ __forceinline__ float half_quantise(const cx<float> (&v)[12], h8 (&q)[3]) {
+  float m = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+  const float inv = m > 0.0f ? 1.0f / m : 0.0f;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      q[j][2 * k] = f32_to_half(v[4 * j + k].re * inv);
+      q[j][2 * k + 1] = f32_to_half(v[4 * j + k].im * inv);
+    }
+  return m;
+}
+
+__device__ __forceinline__ void store_spinor(h8* __restrict__ p, long /*V*/, int s,
+                                             const cx<float> (&v)[12]) {
+  h8 q[3];
+  const float m = half_quantise(v, q);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) __builtin_nontemporal_store(q[j], p + half_unit(s, j));
+  __builtin_nontemporal_store(m, reinterpret_cast<float*>(p) + half_scale_index(s));
 }
 
 // Spinors staged in LDS use the same plane layout over the n sites of a tile.
@@ -170,6 +255,27 @@ __device__ __forceinline__ void load_link(const float2* __restrict__ p, long V, 
     for (int k = 0; k < 9; ++k) {
       const float2 t = p[pidx(s, mu * 9 + k, 36, V)];
       u[k] = {t.x, t.y};
+    }
+  }
+}
+
+template <bool C12>
+__device__ __forceinline__ void load_link(const h2* __restrict__ p, long V, int mu, int s,
+                                          cx<float> (&u)[9]) {
+  if constexpr (C12) {
+    const h4* q = reinterpret_cast<const h4*>(p);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const h4 t = q[pidx(s, mu * 3 + j, 12, V)];
+      u[2 * j] = {static_cast<float>(t.x), static_cast<float>(t.y)};
+      u[2 * j + 1] = {static_cast<float>(t.z), static_cast<float>(t.w)};
+    }
+    rebuild_row2(u);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const h2 t = p[pidx(s, mu * 9 + k, 36, V)];
+      u[k] = {static_cast<float>(t.x), static_cast<float>(t.y)};
     }
   }
 }

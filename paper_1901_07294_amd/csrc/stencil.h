@@ -84,9 +84,8 @@ __device__ __forceinline__ void su3_mul(const cx<R> (&u)[9], const cx<R> (&h)[6]
 
 // One hop with the neighbour spinor already in registers and the link of
 // direction MU at site ls loaded from the packed gauge field.
-template <int MU, int S, bool C12, typename R>
-__device__ __forceinline__ void hop_psi(const cx<R> (&psi)[12],
-                                        const typename Packed<R>::L* __restrict__ links, long V,
+template <int MU, int S, bool C12, typename LV, typename R>
+__device__ __forceinline__ void hop_psi(const cx<R> (&psi)[12], const LV* __restrict__ links, long V,
                                         int ls, cx<R> (&acc)[12]) {
   cx<R> u[9];
   load_link<C12>(links, V, MU, ls, u);
@@ -98,13 +97,12 @@ __device__ __forceinline__ void hop_psi(const cx<R> (&psi)[12],
 }
 
 // One hop: neighbour spinor at site n, link of direction MU at site ls.
-template <int MU, int S, bool C12, typename R>
-__device__ __forceinline__ void hop(const typename Packed<R>::S* __restrict__ in,
-                                    const typename Packed<R>::L* __restrict__ links, long V, int n,
-                                    int ls, cx<R> (&acc)[12]) {
+template <int MU, int S, bool C12, typename SV, typename LV, typename R>
+__device__ __forceinline__ void hop(const SV* __restrict__ in, const LV* __restrict__ links, long V,
+                                    int n, int ls, cx<R> (&acc)[12]) {
   cx<R> psi[12];
   load_spinor(in, V, n, psi);
-  hop_psi<MU, S, C12, R>(psi, links, V, ls, acc);
+  hop_psi<MU, S, C12>(psi, links, V, ls, acc);
 }
 
 // out = diag * psi - acc / 2, optionally times gamma5 (negates spins 2, 3).
@@ -114,7 +112,7 @@ __device__ __forceinline__ void epilogue(const cx<R> (&psi)[12], const cx<R> (&a
   const R half = R(0.5);
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
-    cx<R> r = {diag * psi[c].re - half * acc[c].re, diag * psi[c].im - half * acc[c].im};
+    cx<R> r = {fmar(diag, psi[c].re, -half * acc[c].re), fmar(diag, psi[c].im, -half * acc[c].im)};
     if (gamma5 && c >= 6) r = -r;
     o[c] = r;
   }

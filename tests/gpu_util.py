@@ -8,9 +8,9 @@ import torch
 import paper_1901_07294_amd.wilson as w
 from paper_1901_07294_amd.buffers import DeviceGauge
 
-PRECS = {"fp64": w.WD_FP64, "fp32": w.WD_FP32}
+PRECS = {"fp64": w.WD_FP64, "fp32": w.WD_FP32, "fp16": w.WD_FP16}
 # relative tolerance against the FP64 oracle on the original FP64 inputs
-TOL = {w.WD_FP64: 1e-13, w.WD_FP32: 1e-6}
+TOL = {w.WD_FP64: 1e-13, w.WD_FP32: 1e-6, w.WD_FP16: 2e-3}
 
 
 def rel(a, b):

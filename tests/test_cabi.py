@@ -56,6 +56,12 @@ def test_version_and_sizes(lib):
     assert w.wd_gauge_bytes(d, w.WD_FP64, 1) == 384 * V
     assert w.wd_gauge_bytes(d, w.WD_FP32, 0) == 288 * V
     assert w.wd_gauge_bytes(d, w.WD_FP32, 1) == 192 * V
+    # FP16 storage: 24 binary16 + one FP32 scale per spinor site; unscaled links
+    assert w.wd_spinor_bytes(d, w.WD_FP16, 12) == 12 * 52 * V
+    assert w.wd_gauge_bytes(d, w.WD_FP16, 0) == 144 * V
+    assert w.wd_gauge_bytes(d, w.WD_FP16, 1) == 96 * V
+    # padding to whole blocks of 64 sites
+    assert w.wd_spinor_bytes((5, 3, 7, 4), w.WD_FP16, 1) == 448 * 52
 
 
 def test_size_queries_reject_bad_arguments(lib):

@@ -187,7 +187,8 @@ def test_error_paths():
     assert _code(w.dslash_apply, g.handle, 0.1, host, b, w.WD_FP64) == w.WD_ERR_INVALID_ARG
     assert _code(w.dslash_apply, g.handle, 0.1, a, a, w.WD_FP64) == w.WD_ERR_INVALID_ARG
     assert _code(w.dslash_apply, g.handle, 0.1, a, b, w.WD_FP32) == w.WD_ERR_INVALID_ARG
-    assert _code(w.dslash_apply, g.handle, 0.1, a, b, w.WD_FP16) == w.WD_ERR_UNSUPPORTED
+    assert _code(w.dslash_apply, g.handle, 0.1, a, b, w.WD_FP16) == w.WD_ERR_INVALID_ARG
+    assert _code(w.dslash_apply, g.handle, 0.1, a, b, 5) == w.WD_ERR_INVALID_ARG
     assert _code(w.dslash_apply, g.handle, 0.1, a, b, w.WD_FP64, flags=4) == w.WD_ERR_INVALID_ARG
     assert _code(w.dslash_apply, None, 0.1, a, b, w.WD_FP64) == w.WD_ERR_INVALID_ARG
     # a buffer that ends before the field does

@@ -24,7 +24,7 @@ def _device():
 SHAPES = [(4, 4, 4, 4), (5, 3, 7, 4), (32, 32, 16, 11), (24, 24, 4, 8), (16, 8, 8, 8)]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
 @pytest.mark.parametrize("dims", SHAPES, ids=lambda d: "x".join(map(str, d)))
 def test_multi_matches_oracle_and_single(dims, prec):
     nrhs = 5
@@ -77,7 +77,7 @@ def test_multi_gamma5_and_limits():
         small.free()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "fp64"])
 def test_multi_24_3_48_twelve_rhs_sampled(prec):
     """24^3 x 48, 12 right-hand sides, near-unity links: sampled sites of every field."""
     dims = (24, 24, 24, 48)
