@@ -167,19 +167,20 @@ WD_API int dslash_apply_multi(const wd_gauge* g, const double* masses_host, int3
  * Sec. II-A of the paper names iterative solvers such as conjugate gradient
  * as where lattice QCD spends its time, dominated by the Dirac operator
  * applied to a quark field. D^dag D = Q^2 with the Hermitian Q = gamma5 D, so
- * every iteration applies dslash twice. With inner = WD_FP32 the iterations
- * run on FP32 fields (g_lo) while the solution is accumulated in FP64 and the
- * residual is recomputed in FP64 (b - D^dag D x with g_hi) whenever the FP32
- * residual has dropped by delta since the last recompute or claims
- * convergence ("reliable updates"); convergence is always decided on that FP64
- * true residual.
+ * every iteration applies dslash twice. With inner = WD_FP32 or WD_FP16 the
+ * iterations run on fields of that precision (g_lo; FP16 storage keeps FP32
+ * arithmetic) while the solution is accumulated in FP64 and the residual is
+ * recomputed in FP64 (b - D^dag D x with g_hi) whenever the inner residual
+ * has dropped by delta since the last recompute or claims convergence
+ * ("reliable updates"); convergence is always decided on that FP64 true
+ * residual.
  * ------------------------------------------------------------------------ */
 
 typedef struct wd_cg_params {
   double tol;          /* stop when |b - D^dag D x| <= tol |b| (FP64 true residual) */
   int32_t max_iter;    /* >= 1; iterations of the inner loop (each: two dslash) */
-  int32_t inner;       /* WD_FP64 (plain CG) or WD_FP32 (mixed precision) */
-  double delta;        /* reliable-update threshold in (0, 1); used with WD_FP32 */
+  int32_t inner;       /* WD_FP64 (plain CG), WD_FP32 or WD_FP16 (mixed precision) */
+  double delta;        /* reliable-update threshold in (0, 1); used with mixed precision */
   int32_t check_every; /* >= 1; iterations between host checks of the residual */
   int32_t x0_given;    /* nonzero: start from the contents of x_dev, else x0 = 0 */
 } wd_cg_params;
@@ -202,8 +203,9 @@ WD_API size_t cg_workspace_bytes(const int32_t dims[4], int32_t nrhs, int32_t in
  * side with its own mass masses_host[k]. b_dev and x_dev hold nrhs packed FP64
  * spinors of g_hi's lattice (wd_spinor_bytes(dims, WD_FP64, nrhs) bytes each;
  * x_dev is the output, and the start vector if params->x0_given). g_hi is an
- * FP64 gauge handle; g_lo an FP32 handle of the same lattice when
- * params->inner == WD_FP32 (ignored otherwise, may be NULL). ws_dev:
+ * FP64 gauge handle; g_lo a handle of the same lattice in the inner precision
+ * when params->inner is WD_FP32 or WD_FP16 (ignored otherwise, may be NULL).
+ * ws_dev:
  * cg_workspace_bytes(...) bytes of caller-owned device memory, not
  * overlapping b_dev or x_dev. stats_host: nrhs entries (may be NULL).
  * Synchronous: work is enqueued on stream and the call returns when every
@@ -237,9 +239,9 @@ typedef struct wd_server wd_server; /* opaque */
 typedef struct wd_server_cfg {
   void* arena_dev;            /* caller-owned device memory; the server owns it until destroyed */
   size_t arena_bytes;
-  int32_t inner;              /* WD_FP32 (mixed precision) or WD_FP64 */
+  int32_t inner;              /* WD_FP32 or WD_FP16 (mixed precision), or WD_FP64 */
   int32_t check_every;        /* >= 1: CG iterations per chunk */
-  double delta;               /* reliable-update threshold (WD_FP32), in (0, 1) */
+  double delta;               /* reliable-update threshold (mixed precision), in (0, 1) */
   int32_t max_rhs_per_group;  /* 1..16 slots per group; also the largest nrhs of a request */
   int32_t n_streams;          /* 1..16 streams the groups are spread over */
 } wd_server_cfg;
@@ -272,8 +274,8 @@ typedef struct wd_server_state {
  * arena must stay valid until wd_server_destroy returns. */
 WD_API int wd_server_create(const wd_server_cfg* cfg, wd_server** out);
 
-/* Packs the canonical complex128 gauge field U_canon_dev (FP64, plus FP32 for
- * mixed precision) into the arena and returns its id; U_canon_dev is not
+/* Packs the canonical complex128 gauge field U_canon_dev (FP64, plus a copy in
+ * the inner precision for mixed precision) into the arena and returns its id; U_canon_dev is not
  * kept. Synchronous. WD_ERR_NOMEM if the arena has no room. */
 WD_API int wd_server_add_gauge(wd_server* s, const int32_t dims[4], const void* U_canon_dev,
                                uint64_t* gauge_id);

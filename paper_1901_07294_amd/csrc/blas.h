@@ -32,20 +32,20 @@ enum : int {
 // What a reduction's result updates (finalize modes).
 enum : int { kFinPap = 0, kFinIterRr = 1, kFinTrueRr = 2, kFinNorm = 3 };
 
-// Workgroups of a reduction over n elements (fixed for a lattice).
-int reduction_blocks(long n);
-
 // n: 16-byte elements per right-hand side of the vectors in precision prec;
-// nhi: FP64 elements per right-hand side; V: lattice sites.
+// nhi: FP64 elements per right-hand side; V: lattice sites. The number of
+// partial sums of a reduction depends only on the lattice and precision.
 hipError_t blas_norm2(const void* v, int prec, long n, long V, const RhsSet& set, double* partials,
                       double* scal, int mode, hipStream_t st);
 hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nhi,
                           long V, const RhsSet& set, double* partials, double* scal, hipStream_t st);
-hipError_t blas_update_p(void* p, const void* r, int prec, long n, const RhsSet& set,
+hipError_t blas_update_p(void* p, const void* r, int prec, long n, long V, const RhsSet& set,
                          const double* scal, hipStream_t st);
 hipError_t blas_residual(void* r, const void* b, long n, long V, const RhsSet& set, double* partials,
                          double* scal, hipStream_t st);
-hipError_t blas_demote(void* lo, const void* hi, long n, long nhi, const RhsSet& set, hipStream_t st);
+// lo (FP32 or FP16) = hi (FP64)
+hipError_t blas_demote(void* lo, const void* hi, int prec, long n, long nhi, long V, const RhsSet& set,
+                       hipStream_t st);
 hipError_t blas_copy(void* dst, const void* src, int prec, long n, const RhsSet& set, hipStream_t st);
 hipError_t blas_zero(void* dst, int prec, long n, const RhsSet& set, hipStream_t st);
 

@@ -1,10 +1,13 @@
 // Vector kernels of the conjugate-gradient solver: fused updates and
 // deterministic reductions over packed spinor fields.
 //
-// A packed field (fields.h) is a flat array of 16-byte elements: 12 per site
-// in FP64 (double2), 6 per site in FP32 (float4), in blocks of 64 sites. The
-// elementwise kernels walk that flat array; the reductions skip the padding
-// sites of the last block. Every reduction is two-stage with a fixed
+// A packed FP64 or FP32 field (fields.h) is a flat array of 16-byte
+// elements: 12 per site in FP64 (double2), 6 per site in FP32 (float4), in
+// blocks of 64 sites. Their elementwise kernels walk that flat array; the
+// reductions skip the padding sites of the last block. An FP16 field shares
+// one scale among the 24 reals of a site, so its kernels work site by site
+// (one thread per site, real sites only), in FP32 arithmetic, and store
+// results requantised. Every reduction is two-stage with a fixed
 // assignment of elements to threads and a fixed combination order, so a sum
 // depends only on the lattice, never on how many right-hand sides are in
 // flight or on timing: results are bitwise reproducible.
@@ -216,6 +219,124 @@ __global__ __launch_bounds__(kThreads) void zero_kernel(T* __restrict__ dst, lon
     dst[k * n + e] = z;
 }
 
+// ------------------------------------------------------------ FP16 fields
+
+__device__ __forceinline__ double site_norm2(const cx<float> (&v)[12]) {
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const double re = v[c].re, im = v[c].im;
+    s = fmar(re, re, fmar(im, im, s));
+  }
+  return s;
+}
+
+// Quantises and stores a site (cached stores: CG vectors are read again at
+// once); returns the squared norm of the values as stored.
+__device__ __forceinline__ double store_half_site(h8* __restrict__ p, long s, const cx<float> (&v)[12]) {
+  h8 q[3];
+  const float m = half_quantise(v, q);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) p[half_unit(s, j)] = q[j];
+  reinterpret_cast<float*>(p)[half_scale_index(s)] = m;
+  double n = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double d = static_cast<float>(q[j][k]) * m;
+      n = fmar(d, d, n);
+    }
+  return n;
+}
+
+#define WD_SITE_LOOP(i, V) \
+  for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < (V); \
+       i += static_cast<long>(gridDim.x) * kThreads)
+
+__global__ __launch_bounds__(kThreads) void norm2_half_kernel(const h8* __restrict__ v, long units,
+                                                              long V, RhsSet set,
+                                                              double* __restrict__ partials) {
+  const int k = set.idx[blockIdx.y];
+  const h8* x = v + k * units;
+  double s = 0.0;
+  WD_SITE_LOOP(i, V) {
+    cx<float> a[12];
+    load_spinor(x, V, static_cast<int>(i), a);
+    s += site_norm2(a);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
+}
+
+// x_hi += alpha p ; r -= alpha Ap (FP32, requantised) ; partial |r|^2
+__global__ __launch_bounds__(kThreads) void update_xr_half_kernel(
+    double2* __restrict__ x, h8* __restrict__ r, const h8* __restrict__ p, const h8* __restrict__ ap,
+    long units, long nhi, long V, RhsSet set, const double* __restrict__ scal,
+    double* __restrict__ partials) {
+  const int k = set.idx[blockIdx.y];
+  const double alpha = scal[k * kScalars + kAlpha];
+  const float a = static_cast<float>(alpha);
+  double2* xk = x + k * nhi;
+  h8* rk = r + k * units;
+  double s = 0.0;
+  WD_SITE_LOOP(i, V) {
+    cx<float> pv[12], rv[12], av[12];
+    load_spinor(p + k * units, V, static_cast<int>(i), pv);
+    load_spinor(rk, V, static_cast<int>(i), rv);
+    load_spinor(ap + k * units, V, static_cast<int>(i), av);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      double2 xe = xk[pidx(i, c, 12, V)];
+      xe.x = fmar(alpha, static_cast<double>(pv[c].re), xe.x);
+      xe.y = fmar(alpha, static_cast<double>(pv[c].im), xe.y);
+      xk[pidx(i, c, 12, V)] = xe;
+      rv[c] = {fmar(-a, av[c].re, rv[c].re), fmar(-a, av[c].im, rv[c].im)};
+    }
+    s += store_half_site(rk, i, rv);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
+}
+
+// p = r + beta p
+__global__ __launch_bounds__(kThreads) void update_p_half_kernel(h8* __restrict__ p,
+                                                                 const h8* __restrict__ r, long units,
+                                                                 long V, RhsSet set,
+                                                                 const double* __restrict__ scal) {
+  const int k = set.idx[blockIdx.y];
+  const float b = static_cast<float>(scal[k * kScalars + kBeta]);
+  h8* pk = p + k * units;
+  WD_SITE_LOOP(i, V) {
+    cx<float> pv[12], rv[12];
+    load_spinor(pk, V, static_cast<int>(i), pv);
+    load_spinor(r + k * units, V, static_cast<int>(i), rv);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) pv[c] = {fmar(b, pv[c].re, rv[c].re), fmar(b, pv[c].im, rv[c].im)};
+    store_half_site(pk, i, pv);
+  }
+}
+
+// lo = FP16(hi): components rounded to FP32, then quantised per site
+__global__ __launch_bounds__(kThreads) void demote_half_kernel(h8* __restrict__ lo,
+                                                               const double2* __restrict__ hi,
+                                                               long units, long nhi, long V,
+                                                               RhsSet set) {
+  const int k = set.idx[blockIdx.y];
+  const double2* hk = hi + k * nhi;
+  WD_SITE_LOOP(i, V) {
+    cx<float> v[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const double2 t = hk[pidx(i, c, 12, V)];
+      v[c] = {static_cast<float>(t.x), static_cast<float>(t.y)};
+    }
+    store_half_site(lo + k * units, i, v);
+  }
+}
+
+#undef WD_SITE_LOOP
+
 // One workgroup per right-hand side: sum its partials in a fixed order and
 // update the scalars. Non-finite or non-positive curvature raises kFlag.
 __global__ __launch_bounds__(kThreads) void finalize_kernel(const double* __restrict__ partials,
@@ -263,46 +384,52 @@ dim3 grid(long n, int nset) {
 
 }  // namespace
 
-int reduction_blocks(long n) { return static_cast<int>(grid(n, 1).x); }
-
 hipError_t blas_norm2(const void* v, int prec, long n, long V, const RhsSet& set, double* partials,
                       double* scal, int mode, hipStream_t st) {
-  const dim3 g = grid(n, set.n);
+  const dim3 g = grid(prec == WD_FP16 ? V : n, set.n);
   if (prec == WD_FP64)
     norm2_partial_kernel<double2><<<g, kThreads, 0, st>>>(static_cast<const double2*>(v), n, V, set, partials);
-  else
+  else if (prec == WD_FP32)
     norm2_partial_kernel<float4><<<g, kThreads, 0, st>>>(static_cast<const float4*>(v), n, V, set, partials);
+  else
+    norm2_half_kernel<<<g, kThreads, 0, st>>>(static_cast<const h8*>(v), n, V, set, partials);
   finalize_kernel<<<set.n, kThreads, 0, st>>>(partials, static_cast<int>(g.x), set, mode, scal);
   return hipGetLastError();
 }
 
 hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nhi,
                           long V, const RhsSet& set, double* partials, double* scal, hipStream_t st) {
-  const dim3 g = grid(n, set.n);
+  const dim3 g = grid(prec == WD_FP16 ? V : n, set.n);
   auto* xh = static_cast<double2*>(x);
   if (prec == WD_FP64)
     update_xr_kernel<double2><<<g, kThreads, 0, st>>>(xh, static_cast<double2*>(r),
                                                        static_cast<const double2*>(p),
                                                        static_cast<const double2*>(ap), n, nhi, V,
                                                        set, scal, partials);
-  else
+  else if (prec == WD_FP32)
     update_xr_kernel<float4><<<g, kThreads, 0, st>>>(xh, static_cast<float4*>(r),
                                                       static_cast<const float4*>(p),
                                                       static_cast<const float4*>(ap), n, nhi, V,
                                                       set, scal, partials);
+  else
+    update_xr_half_kernel<<<g, kThreads, 0, st>>>(xh, static_cast<h8*>(r), static_cast<const h8*>(p),
+                                                  static_cast<const h8*>(ap), n, nhi, V, set, scal,
+                                                  partials);
   finalize_kernel<<<set.n, kThreads, 0, st>>>(partials, static_cast<int>(g.x), set, kFinIterRr, scal);
   return hipGetLastError();
 }
 
-hipError_t blas_update_p(void* p, const void* r, int prec, long n, const RhsSet& set,
+hipError_t blas_update_p(void* p, const void* r, int prec, long n, long V, const RhsSet& set,
                          const double* scal, hipStream_t st) {
-  const dim3 g = grid(n, set.n);
   if (prec == WD_FP64)
-    update_p_kernel<double2><<<g, kThreads, 0, st>>>(static_cast<double2*>(p),
-                                                      static_cast<const double2*>(r), n, set, scal);
+    update_p_kernel<double2><<<grid(n, set.n), kThreads, 0, st>>>(
+        static_cast<double2*>(p), static_cast<const double2*>(r), n, set, scal);
+  else if (prec == WD_FP32)
+    update_p_kernel<float4><<<grid(n, set.n), kThreads, 0, st>>>(
+        static_cast<float4*>(p), static_cast<const float4*>(r), n, set, scal);
   else
-    update_p_kernel<float4><<<g, kThreads, 0, st>>>(static_cast<float4*>(p),
-                                                     static_cast<const float4*>(r), n, set, scal);
+    update_p_half_kernel<<<grid(V, set.n), kThreads, 0, st>>>(static_cast<h8*>(p),
+                                                              static_cast<const h8*>(r), n, V, set, scal);
   return hipGetLastError();
 }
 
@@ -315,12 +442,21 @@ hipError_t blas_residual(void* r, const void* b, long n, long V, const RhsSet& s
   return hipGetLastError();
 }
 
-hipError_t blas_demote(void* lo, const void* hi, long n, long nhi, const RhsSet& set, hipStream_t st) {
-  demote_kernel<<<grid(n, set.n), kThreads, 0, st>>>(static_cast<float4*>(lo),
-                                                     static_cast<const double2*>(hi), n, nhi, set);
+hipError_t blas_demote(void* lo, const void* hi, int prec, long n, long nhi, long V, const RhsSet& set,
+                       hipStream_t st) {
+  if (prec == WD_FP32)
+    demote_kernel<<<grid(n, set.n), kThreads, 0, st>>>(static_cast<float4*>(lo),
+                                                       static_cast<const double2*>(hi), n, nhi, set);
+  else if (prec == WD_FP16)
+    demote_half_kernel<<<grid(V, set.n), kThreads, 0, st>>>(static_cast<h8*>(lo),
+                                                            static_cast<const double2*>(hi), n, nhi, V,
+                                                            set);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
+// Copies and zero fills move whole 16-byte elements (FP16 fields included).
 hipError_t blas_copy(void* dst, const void* src, int prec, long n, const RhsSet& set, hipStream_t st) {
   if (prec == WD_FP64)
     copy_kernel<double2><<<grid(n, set.n), kThreads, 0, st>>>(static_cast<double2*>(dst),

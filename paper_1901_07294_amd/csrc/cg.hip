@@ -1,15 +1,16 @@
 // Conjugate gradient on the normal equations D^dag D x = b, plain FP64 or
-// with FP32 inner iterations and FP64 reliable updates.
+// with FP32 or FP16-storage inner iterations and FP64 reliable updates.
 //
 // The paper (Sec. II-A) names iterative solvers such as conjugate gradient as
 // where lattice QCD spends its time, dominated by the Dirac operator applied
 // to a quark field; its related work cites mixed-precision GPU solvers. Here
 // A = D^dag D = Q^2 with the Hermitian Q = gamma5 D, so one CG iteration is two
 // dslash applications (gamma5 folded into their epilogue) and <p, A p> =
-// |Q p|^2. With FP32 inner iterations the solution is accumulated in FP64, and
-// whenever the iterated FP32 residual has fallen by the factor delta since the
-// last true residual (or claims convergence), the residual is recomputed in
-// FP64 as b - A x ("reliable update") and the FP32 residual restarted from it.
+// |Q p|^2. With lower-precision inner iterations (FP32, or FP16 storage with
+// FP32 arithmetic) the solution is accumulated in FP64, and whenever the
+// iterated residual has fallen by the factor delta since the last true
+// residual (or claims convergence), the residual is recomputed in FP64 as
+// b - A x ("reliable update") and the inner residual restarted from it.
 // Convergence is always judged on that FP64 true residual.
 //
 // Scalars (alpha, beta, <r,r>) stay on the device; the host reads them only
@@ -31,13 +32,13 @@ namespace wd {
 size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
 // Plain FP64 CG keeps r, p, t, Ap in FP64 (the true-residual recompute reuses
-// t and Ap); mixed CG adds FP64 r and t.
+// r and t); mixed CG adds FP64 r and t.
 CgLayout cg_layout(long V, int slots, int inner) {
   CgLayout w;
   const size_t hi = align256(static_cast<size_t>(packed_sites(V)) * slots * spinor_site_bytes(WD_FP64));
   const size_t lo = align256(static_cast<size_t>(packed_sites(V)) * slots * spinor_site_bytes(inner));
   size_t o = 0;
-  if (inner == WD_FP32) {
+  if (inner != WD_FP64) {
     w.r_hi = o; o += hi;
     w.t_hi = o; o += hi;
   }
@@ -45,7 +46,7 @@ CgLayout cg_layout(long V, int slots, int inner) {
   w.p = o; o += lo;
   w.t = o; o += lo;
   w.ap = o; o += lo;
-  if (inner != WD_FP32) {
+  if (inner == WD_FP64) {
     w.r_hi = w.r;
     w.t_hi = w.t;
   }
@@ -78,7 +79,8 @@ CgEngine::CgEngine(const wd_gauge* ghi, const wd_gauge* glo, int inner, int slot
     : ghi_(ghi), glo_(glo ? glo : ghi), inner_(inner), slots_(slots), b_(b), x_(x), ws_(ws), st_(st) {
   V_ = ghi->V;
   nhi_ = packed_sites(V_) * 12;
-  nlo_ = packed_sites(V_) * (inner_ == WD_FP64 ? 12 : 6);
+  nlo_ = inner_ == WD_FP64 ? spinor_units<double>(V_)
+                           : inner_ == WD_FP32 ? spinor_units<float>(V_) : spinor_units<_Float16>(V_);
   lay_ = cg_layout(V_, slots, inner_);
   partials_ = reinterpret_cast<double*>(at(ws_, lay_.partials));
   scal_ = reinterpret_cast<double*>(at(ws_, lay_.scal));
@@ -98,8 +100,9 @@ int CgEngine::start(const RhsSet& set, bool x0_given) {
     if (rc == WD_OK)
       rc = launch_status(blas_norm2(at(ws_, lay_.r_hi), WD_FP64, nhi_, V_, set, partials_, scal_,
                                     kFinTrueRr, st_), "cg: |r0|");
-    if (rc == WD_OK && inner_ == WD_FP32)
-      rc = launch_status(blas_demote(at(ws_, lay_.r), at(ws_, lay_.r_hi), nlo_, nhi_, set, st_), "cg: demote");
+    if (rc == WD_OK && inner_ != WD_FP64)
+      rc = launch_status(blas_demote(at(ws_, lay_.r), at(ws_, lay_.r_hi), inner_, nlo_, nhi_, V_, set, st_),
+                         "cg: demote");
   }
   if (rc != WD_OK) return rc;
   return launch_status(blas_copy(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, set, st_), "cg: p0");
@@ -120,7 +123,7 @@ int CgEngine::iterate(const RhsSet& set) {
     rc = launch_status(blas_update_xr(x_, at(ws_, lay_.r), at(ws_, lay_.p), at(ws_, lay_.ap), inner_,
                                       nlo_, nhi_, V_, set, partials_, scal_, st_), "cg: x, r");
   if (rc == WD_OK)
-    rc = launch_status(blas_update_p(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, set, scal_, st_),
+    rc = launch_status(blas_update_p(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, V_, set, scal_, st_),
                        "cg: p");
   return rc;
 }
@@ -136,8 +139,8 @@ int CgEngine::refresh(const RhsSet& set) {
   if (rc == WD_OK)
     rc = launch_status(blas_residual(at(ws_, lay_.r_hi), b_, nhi_, V_, set, partials_, scal_, st_),
                        "cg: b - A x");
-  if (rc == WD_OK && inner_ == WD_FP32)
-    rc = launch_status(blas_demote(at(ws_, lay_.r), at(ws_, lay_.r_hi), nlo_, nhi_, set, st_),
+  if (rc == WD_OK && inner_ != WD_FP64)
+    rc = launch_status(blas_demote(at(ws_, lay_.r), at(ws_, lay_.r_hi), inner_, nlo_, nhi_, V_, set, st_),
                        "cg: demote");
   return rc;
 }
@@ -178,7 +181,7 @@ int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, i
   };
   std::vector<int> status(nrhs, WD_PENDING), iters(nrhs, 0), updates(nrhs, 0), all;
   for (int k = 0; k < nrhs; ++k) all.push_back(k);
-  const bool mixed = prm.inner == WD_FP32;
+  const bool mixed = prm.inner != WD_FP64;
 
   int rc = eng.start(set_of(all), prm.x0_given != 0);
   if (rc == WD_OK) rc = read();
@@ -264,7 +267,7 @@ extern "C" {
 size_t cg_workspace_bytes(const int32_t dims[4], int32_t nrhs, int32_t inner) {
   long V = 0;
   if (check_dims(dims, &V) != WD_OK || nrhs < 1 || nrhs > kMaxRhs) return 0;
-  if (inner != WD_FP64 && inner != WD_FP32) return 0;
+  if (inner != WD_FP64 && inner != WD_FP32 && inner != WD_FP16) return 0;
   return cg_layout(V, nrhs, inner).bytes;
 }
 
@@ -283,11 +286,13 @@ int cg_solve_normal(const wd_gauge* g_hi, const wd_gauge* g_lo, const double* ma
       return set_error(WD_ERR_UNSUPPORTED, "nrhs %d outside 1..%d", nrhs, kMaxRhs);
     if (!(p.tol > 0.0) || p.max_iter < 1 || p.check_every < 1)
       return set_error(WD_ERR_INVALID_ARG, "need tol > 0, max_iter >= 1, check_every >= 1");
-    if (p.inner != WD_FP64 && p.inner != WD_FP32)
-      return set_error(WD_ERR_UNSUPPORTED, "inner precision %d not supported", p.inner);
-    if (p.inner == WD_FP32) {
+    if (p.inner != WD_FP64 && p.inner != WD_FP32 && p.inner != WD_FP16)
+      return set_error(WD_ERR_INVALID_ARG, "unknown inner precision %d", p.inner);
+    if (p.inner != WD_FP64) {
       if ((rc = check_gauge(g_lo)) != WD_OK) return rc;
-      if (g_lo->prec != WD_FP32) return set_error(WD_ERR_INVALID_ARG, "g_lo must be an FP32 gauge field");
+      if (g_lo->prec != p.inner)
+        return set_error(WD_ERR_INVALID_ARG, "g_lo must be a gauge field of the inner precision %d",
+                         p.inner);
       for (int i = 0; i < 4; ++i)
         if (g_lo->dims[i] != g_hi->dims[i])
           return set_error(WD_ERR_SHAPE, "g_lo and g_hi have different lattices");
@@ -307,7 +312,7 @@ int cg_solve_normal(const wd_gauge* g_hi, const wd_gauge* g_lo, const double* ma
     if (overlaps(b_dev, vec, x_dev, vec) || overlaps(b_dev, vec, ws_dev, need) ||
         overlaps(x_dev, vec, ws_dev, need))
       return set_error(WD_ERR_INVALID_ARG, "b_dev, x_dev and ws_dev must not overlap");
-    return solve_sync(g_hi, p.inner == WD_FP32 ? g_lo : g_hi, masses_host, nrhs, b_dev, x_dev, p,
+    return solve_sync(g_hi, p.inner != WD_FP64 ? g_lo : g_hi, masses_host, nrhs, b_dev, x_dev, p,
                       stats_host, ws_dev, stream);
   } catch (...) {
     return set_error(WD_ERR_INTERNAL, "unexpected exception in cg_solve_normal");

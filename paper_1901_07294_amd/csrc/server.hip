@@ -182,6 +182,11 @@ size_t vec_bytes(long V, int n) {
   return align256(static_cast<size_t>(packed_sites(V)) * n * spinor_site_bytes(WD_FP64));
 }
 
+// Arena bytes of the inner-precision copy of a gauge field (none for FP64).
+size_t inner_gauge_bytes(const int32_t dims[4], int inner) {
+  return inner == WD_FP64 ? 0 : align256(wd_gauge_bytes(dims, inner, 0));
+}
+
 size_t group_bytes(long V, int S, int inner) {
   return 2 * vec_bytes(V, S) + cg_layout(V, S, inner).bytes;
 }
@@ -237,7 +242,7 @@ Group* wd_server::make_group(GaugeEntry* ge) {
   void* b = mem;
   void* x = mem + vec_bytes(ge->V, S);
   void* ws = mem + 2 * vec_bytes(ge->V, S);
-  g->eng = std::make_unique<CgEngine>(ge->hi, cfg.inner == WD_FP32 ? ge->lo : ge->hi, cfg.inner, S, b,
+  g->eng = std::make_unique<CgEngine>(ge->hi, cfg.inner != WD_FP64 ? ge->lo : ge->hi, cfg.inner, S, b,
                                       x, ws, g->stream);
   g->slots.assign(S, Slot{});
   ge->groups++;
@@ -348,7 +353,7 @@ void wd_server::finish_slot(Group& g, int k, int status) {
 
 // The group's event has completed: act on the scalars it brought back.
 bool wd_server::advance(Group& g) {
-  const bool mixed = cfg.inner == WD_FP32;
+  const bool mixed = cfg.inner != WD_FP64;
   if (g.phase == Group::kChunk) {
     g.refreshing.clear();
     for (int k = 0; k < g.S; ++k) {
@@ -491,13 +496,13 @@ int wd_server_create(const wd_server_cfg* cfg, wd_server** out) {
     clear_error();
     if (cfg == nullptr || out == nullptr) return set_error(WD_ERR_INVALID_ARG, "cfg and out must not be NULL");
     *out = nullptr;
-    if (cfg->inner != WD_FP64 && cfg->inner != WD_FP32)
-      return set_error(WD_ERR_UNSUPPORTED, "inner precision %d not supported", cfg->inner);
+    if (cfg->inner != WD_FP64 && cfg->inner != WD_FP32 && cfg->inner != WD_FP16)
+      return set_error(WD_ERR_INVALID_ARG, "unknown inner precision %d", cfg->inner);
     if (cfg->check_every < 1 || cfg->max_rhs_per_group < 1 || cfg->max_rhs_per_group > kMaxRhs ||
         cfg->n_streams < 1 || cfg->n_streams > 16)
       return set_error(WD_ERR_INVALID_ARG,
                        "need check_every >= 1, max_rhs_per_group in 1..16, n_streams in 1..16");
-    if (cfg->inner == WD_FP32 && !(cfg->delta > 0.0 && cfg->delta < 1.0))
+    if (cfg->inner != WD_FP64 && !(cfg->delta > 0.0 && cfg->delta < 1.0))
       return set_error(WD_ERR_INVALID_ARG, "delta must lie in (0, 1)");
     int rc = check_device_range(cfg->arena_dev, cfg->arena_bytes, "arena_dev");
     if (rc != WD_OK) return rc;
@@ -534,7 +539,7 @@ int wd_server_add_gauge(wd_server* s, const int32_t dims[4], const void* U_canon
     if ((rc = check_device_range(U_canon_dev, static_cast<size_t>(V) * 36 * 16, "U_canon_dev")) != WD_OK)
       return rc;
     const size_t bhi = align256(wd_gauge_bytes(dims, WD_FP64, 0));
-    const size_t blo = s->cfg.inner == WD_FP32 ? align256(wd_gauge_bytes(dims, WD_FP32, 0)) : 0;
+    const size_t blo = inner_gauge_bytes(dims, s->cfg.inner);
     auto ge = std::make_unique<GaugeEntry>();
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -549,7 +554,7 @@ int wd_server_add_gauge(wd_server* s, const int32_t dims[4], const void* U_canon
     }
     rc = wd_gauge_import(dims, U_canon_dev, WD_FP64, 0, ge->mem, bhi, st, &ge->hi);
     if (rc == WD_OK && blo)
-      rc = wd_gauge_import(dims, U_canon_dev, WD_FP32, 0, ge->mem + bhi, blo, st, &ge->lo);
+      rc = wd_gauge_import(dims, U_canon_dev, s->cfg.inner, 0, ge->mem + bhi, blo, st, &ge->lo);
     if (rc == WD_OK && hipStreamSynchronize(st) != hipSuccess)
       rc = set_error(WD_ERR_DEVICE, "packing the gauge field failed");
     (void)hipStreamDestroy(st);
@@ -614,8 +619,8 @@ int cg_submit(wd_server* s, const wd_request* req, uint64_t* ticket) {
       size_t gauges = 0;
       lk.lock();
       for (auto& [id, g] : s->gauges)
-        if (!g->removing) gauges += align256(wd_gauge_bytes(g->dims, WD_FP64, 0)) +
-                                    (s->cfg.inner == WD_FP32 ? align256(wd_gauge_bytes(g->dims, WD_FP32, 0)) : 0);
+        if (!g->removing)
+          gauges += align256(wd_gauge_bytes(g->dims, WD_FP64, 0)) + inner_gauge_bytes(g->dims, s->cfg.inner);
       lk.unlock();
       if (group_bytes(ge->V, s->cfg.max_rhs_per_group, s->cfg.inner) + gauges > s->cfg.arena_bytes)
         return set_error(WD_ERR_NOMEM, "a solve group of this lattice cannot fit beside the gauge fields");

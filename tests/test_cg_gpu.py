@@ -35,7 +35,7 @@ def solve(U, masses, bs, inner, tol=1e-10, max_iter=20000, delta=0.1, check_ever
     """Solve through the C ABI; bs: [nrhs, T, Z, Y, X, 4, 3]. Returns (rc, xs, stats)."""
     nrhs = len(masses)
     ghi = DeviceGauge(U, w.WD_FP64)
-    glo = DeviceGauge(U, w.WD_FP32) if inner == w.WD_FP32 else None
+    glo = DeviceGauge(U, inner) if inner != w.WD_FP64 else None
     b = ghi.pack(bs, nrhs=nrhs)
     x = ghi.pack(x0, nrhs=nrhs) if x0 is not None else ghi.spinor(nrhs)
     ws = torch.empty(w.cg_workspace_bytes(ghi.dims, nrhs, inner), dtype=torch.uint8, device="cuda")
@@ -47,10 +47,10 @@ def solve(U, masses, bs, inner, tol=1e-10, max_iter=20000, delta=0.1, check_ever
     return rc, (xs if nrhs > 1 else xs[None]), stats, x
 
 
-INNER = {"fp64": w.WD_FP64, "fp32": w.WD_FP32}
+INNER = {"fp64": w.WD_FP64, "fp32": w.WD_FP32, "fp16": w.WD_FP16}
 
 
-@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "fp16"])
 def test_cg_dense_2222(inner):
     dims = (2, 2, 2, 2)
     U = li.near_unity_gauge(dims, 91, 0.3)
@@ -66,7 +66,7 @@ def test_cg_dense_2222(inner):
     assert stats[0]["true_rel_residual"] <= 1e-12
 
 
-@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "fp16"])
 def test_cg_matches_oracle_cg(inner):
     dims = (8, 4, 4, 6)
     U = li.near_unity_gauge(dims, 4001, 0.3)
@@ -80,12 +80,12 @@ def test_cg_matches_oracle_cg(inner):
     assert abs(res - stats[0]["true_rel_residual"]) <= 1e-3 * 1e-10 + 1e-14
     # |x - x_ref| / |x_ref| <= kappa * (tol_gpu + tol_ref); kappa <= ((8+m)/m)^2 bounded loosely
     assert rel(xs[0], x_ref) <= 1e-4
-    if inner == "fp32":
+    if inner != "fp64":
         assert stats[0]["reliable_updates"] >= 2
     print("iters", stats[0]["iters"], "oracle iters", it_ref, "updates", stats[0]["reliable_updates"])
 
 
-@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "fp16"])
 def test_cg_24_4_near_unity(inner):
     """The mixed-precision solver configuration: 24^4, m = 0.05, eps = 0.3, tol 1e-10."""
     dims = (24, 24, 24, 24)
@@ -105,7 +105,7 @@ def test_cg_multi_rhs_equals_alone():
     U = li.near_unity_gauge(dims, 77, 0.3)
     bs = li.gaussian_spinors(dims, [78, 79, 80])
     masses = [0.05, 0.2, 0.5]
-    for inner in (w.WD_FP64, w.WD_FP32):
+    for inner in (w.WD_FP64, w.WD_FP32, w.WD_FP16):
         rc, xs, stats, _ = solve(U, masses, bs, inner)
         assert rc == w.WD_OK, stats
         for k in range(3):
@@ -128,8 +128,9 @@ def test_cg_start_from_solution_and_zero_rhs():
     rc2, xs2, stats2, _ = solve(U, [m], b[None], w.WD_FP64, x0=xs[0])
     assert rc2 == w.WD_OK and stats2[0]["iters"] == 0
     assert np.array_equal(xs2[0], xs[0])
-    rc3, xs3, stats3, _ = solve(U, [m], np.zeros_like(b)[None], w.WD_FP32)
-    assert rc3 == w.WD_OK and stats3[0]["iters"] == 0 and not np.any(xs3[0])
+    for inner in (w.WD_FP32, w.WD_FP16):
+        rc3, xs3, stats3, _ = solve(U, [m], np.zeros_like(b)[None], inner)
+        assert rc3 == w.WD_OK and stats3[0]["iters"] == 0 and not np.any(xs3[0])
 
 
 def test_cg_not_converged_and_numeric():
@@ -170,7 +171,8 @@ def test_cg_argument_errors():
     assert code(nrhs=17, masses=[0.1] * 17) == w.WD_ERR_UNSUPPORTED
     assert code(params=dict(good, tol=0.0)) == w.WD_ERR_INVALID_ARG
     assert code(params=dict(good, delta=1.5)) == w.WD_ERR_INVALID_ARG
-    assert code(params=dict(good, inner=w.WD_FP16)) == w.WD_ERR_UNSUPPORTED
+    assert code(params=dict(good, inner=w.WD_FP16)) == w.WD_ERR_INVALID_ARG  # g_lo is FP32
+    assert code(params=dict(good, inner=7)) == w.WD_ERR_INVALID_ARG
     assert code(g_lo=None) == w.WD_ERR_INVALID_ARG
     assert code(g_lo=ghi.handle) == w.WD_ERR_INVALID_ARG
     assert code(g_hi=glo.handle) == w.WD_ERR_INVALID_ARG

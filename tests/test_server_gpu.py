@@ -62,7 +62,8 @@ def make_server(arena_bytes, **kw):
     return srv, arena
 
 
-def test_server_mix_alone_equals_mix_and_residuals():
+@pytest.mark.parametrize("inner", ["fp32", "fp16"])
+def test_server_mix_alone_equals_mix_and_residuals(inner):
     lats = [Lattice((8, 8, 8, 8), 501), Lattice((16, 8, 8, 4), 502)]
     rng = np.random.default_rng(5000)
     reqs = []  # (lattice index, masses, b canonical [nrhs,...])
@@ -74,7 +75,8 @@ def test_server_mix_alone_equals_mix_and_residuals():
         reqs.append((li_, masses, b))
 
     def run(subset):
-        srv, arena = make_server(1 << 30, check_every=4, max_rhs_per_group=8, n_streams=4)
+        srv, arena = make_server(1 << 30, inner={"fp32": w.WD_FP32, "fp16": w.WD_FP16}[inner],
+                                 check_every=4, max_rhs_per_group=8, n_streams=4)
         try:
             gids = [w.wd_server_add_gauge(srv, L.dims, L.Ud) for L in lats]
             bufs, tickets = {}, []
