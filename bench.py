@@ -1,6 +1,6 @@
 """Benchmark of the Wilson-Dirac operator on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32] [--c12]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32|fp16] [--c12]
 
 A step is one application of dslash_apply (D = (4+m) - H/2, periodic, m = 0.1)
 to a Gaussian spinor with random SU(3) links on the 32^3 x 64 lattice
@@ -28,19 +28,27 @@ HBM_PEAK_GBS = 8000.0
 DIMS = (32, 32, 32, 64)
 CONFIG_INDEX = 2          # seeds of the production-lattice configuration
 
+# Bytes per site of a packed spinor and of one packed link (full or 12-real).
+SPINOR_BYTES = {"fp64": 192, "fp32": 96, "fp16": 52}   # FP16: 24 binary16 + FP32 scale
+REAL_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
+
+
 # Compulsory HBM bytes per site: 4 links + spinor in + spinor out.
 def compulsory_bytes(prec: str, c12: bool) -> int:
-    real = 8 if prec == "fp64" else 4
-    return real * (4 * (12 if c12 else 18) + 24 + 24)
+    return REAL_BYTES[prec] * 4 * (12 if c12 else 18) + 2 * SPINOR_BYTES[prec]
 
 
 # HBM traffic of the dslash kernel measured with rocprofv3 --pmc (FETCH_SIZE,
 # WRITE_SIZE), scaled by the same counters on a plain copy of known size; valid
 # only for the kernel sources it was measured on (hash below), else null.
 TRAFFIC = {
-    # FETCH_SIZE 880,922.6 KiB x 2.0 + WRITE_SIZE 393,273.7 KiB x 1.0 (copy-calibrated)
-    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "f389be291df978d3",
-                                       "bytes_per_launch": 2206841795},
+    # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (copy-calibrated KiB per dispatch)
+    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "7188aadc38ffeaf4",   # 878,470.2 / 393,376.8
+                                       "bytes_per_launch": 2201924832},
+    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "7188aadc38ffeaf4",   # 482,661.4 / 196,608.0
+                                       "bytes_per_launch": 1189817184},
+    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "7188aadc38ffeaf4",   # 229,864.7 / 106,496.0
+                                       "bytes_per_launch": 579814752},
 }
 KERNEL_SOURCES = ["paper_1901_07294_amd/csrc/dslash.hip", "paper_1901_07294_amd/csrc/stencil.h",
                   "paper_1901_07294_amd/csrc/fields.h", "paper_1901_07294_amd/csrc/cplx.h"]
@@ -59,7 +67,7 @@ def parse(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--prec", choices=["fp64", "fp32", "fp16"], default="fp64")
     ap.add_argument("--c12", action="store_true", help="12-real link compression")
     ap.add_argument("--dims", type=str, default=",".join(map(str, DIMS)))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -104,15 +112,17 @@ def time_applies(torch, w, g, src, dst, mass, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms per apply
 
 
-def bench_multi(torch, w, li, DeviceGauge, steps=50, warmup=5):
-    """12 right-hand sides on 24^3 x 48, near-unity links, FP32: one fused launch
-    against 12 single launches."""
+def bench_multi(torch, w, li, DeviceGauge, prec="fp32", steps=50, warmup=5, inputs=None):
+    """12 right-hand sides on 24^3 x 48, near-unity links, FP32 or FP16 storage:
+    one fused launch against 12 single launches."""
     dims, nrhs = (24, 24, 24, 48), 12
     V = li.volume(dims)
-    U = li.near_unity_gauge(dims, li.seed_gauge(3), 0.3)
-    psis = li.gaussian_spinors(dims, [li.seed_spinor(3, k) for k in range(nrhs)])
+    if inputs is None:
+        inputs = (li.near_unity_gauge(dims, li.seed_gauge(3), 0.3),
+                  li.gaussian_spinors(dims, [li.seed_spinor(3, k) for k in range(nrhs)]))
+    U, psis = inputs
     masses = [0.1] * nrhs
-    g = DeviceGauge(U, w.WD_FP32)
+    g = DeviceGauge(U, {"fp32": w.WD_FP32, "fp16": w.WD_FP16}[prec])
     src = g.pack(psis, nrhs=nrhs)
     dst = g.spinor(nrhs)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -132,8 +142,8 @@ def bench_multi(torch, w, li, DeviceGauge, steps=50, warmup=5):
     one = g.spinor(1)
     res = g.spinor(1)
     single = timed(lambda: w.dslash_apply(g.handle, 0.1, one, res, g.prec)) * nrhs
-    comp = 4 * (4 * 18 + nrhs * 48)  # FP32 bytes/site: links once + 12 x (in + out)
-    return {"workload": "wilson_dslash_multi_24x24x24x48_x12", "prec": "fp32", "links": "full",
+    comp = REAL_BYTES[prec] * 4 * 18 + nrhs * 2 * SPINOR_BYTES[prec]  # links once + 12 x (in + out)
+    return {"workload": "wilson_dslash_multi_24x24x24x48_x12", "prec": prec, "links": "full",
             "gauge": "near-unity eps=0.3", "ms_per_apply": round(fused, 4),
             "gflops": round(nrhs * FLOPS_PER_SITE * V / (fused / 1e3) / 1e9, 1),
             "pct_hbm_peak": round(100 * comp * V / (fused / 1e3) / 1e9 / HBM_PEAK_GBS, 2),
@@ -142,30 +152,33 @@ def bench_multi(torch, w, li, DeviceGauge, steps=50, warmup=5):
 
 def bench_cg(torch, w, li, DeviceGauge, reps=3):
     """Solves of D^dag D x = b on 24^4, m = 0.05, near-unity links, to a true
-    residual of 1e-10: plain FP64 CG against FP32 inner + FP64 reliable updates."""
+    residual of 1e-10: plain FP64 CG against FP32 or FP16-storage inner
+    iterations with FP64 reliable updates."""
     dims, m = (24, 24, 24, 24), 0.05
     U = li.near_unity_gauge(dims, li.seed_gauge(4), 0.3)
     b = li.gaussian_spinor(dims, li.seed_spinor(4))
     ghi = DeviceGauge(U, w.WD_FP64)
-    glo = DeviceGauge(U, w.WD_FP32)
+    glo = {w.WD_FP64: ghi, w.WD_FP32: DeviceGauge(U, w.WD_FP32), w.WD_FP16: DeviceGauge(U, w.WD_FP16)}
     bd = ghi.pack(b)
     x = ghi.spinor(1)
     out = {"workload": "cg_normal_24x24x24x24_m0.05", "tol": 1e-10, "gauge": "near-unity eps=0.3"}
-    for name, inner in (("fp64", w.WD_FP64), ("mixed_fp32", w.WD_FP32)):
+    for name, inner in (("fp64", w.WD_FP64), ("mixed_fp32", w.WD_FP32), ("mixed_fp16", w.WD_FP16)):
         ws = torch.empty(w.cg_workspace_bytes(dims, 1, inner), dtype=torch.uint8, device="cuda")
         params = dict(tol=1e-10, max_iter=20000, inner=inner, delta=0.1, check_every=8, x0_given=0)
-        w.cg_solve_normal(ghi.handle, glo.handle, [m], 1, bd, x, params, ws)  # warm-up
+        gl = glo[inner].handle
+        w.cg_solve_normal(ghi.handle, gl, [m], 1, bd, x, params, ws)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            rc, st = w.cg_solve_normal(ghi.handle, glo.handle, [m], 1, bd, x, params, ws)
+            rc, st = w.cg_solve_normal(ghi.handle, gl, [m], 1, bd, x, params, ws)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         out[name] = {"status": rc, "solves_per_s": round(1.0 / dt, 2), "ms_per_solve": round(dt * 1e3, 2),
                      "iters": st[0]["iters"], "reliable_updates": st[0]["reliable_updates"],
                      "true_rel_residual": st[0]["true_rel_residual"]}
         del ws
-    out["mixed_speedup"] = round(out["fp64"]["ms_per_solve"] / out["mixed_fp32"]["ms_per_solve"], 3)
+    out["mixed_fp32_speedup"] = round(out["fp64"]["ms_per_solve"] / out["mixed_fp32"]["ms_per_solve"], 3)
+    out["mixed_fp16_speedup"] = round(out["fp64"]["ms_per_solve"] / out["mixed_fp16"]["ms_per_solve"], 3)
     return out
 
 
@@ -296,7 +309,7 @@ def main(argv=None):
     dims = tuple(int(v) for v in args.dims.split(","))
     V = li.volume(dims)
     mass = 0.1
-    prec_id = {"fp64": w.WD_FP64, "fp32": w.WD_FP32}
+    prec_id = {"fp64": w.WD_FP64, "fp32": w.WD_FP32, "fp16": w.WD_FP16}
     print(f"[bench] generating inputs dims={dims}", file=sys.stderr, flush=True)
     t0 = time.time()
     U = li.random_gauge(dims, li.seed_gauge(CONFIG_INDEX))
@@ -333,12 +346,13 @@ def main(argv=None):
     sites = rng.choice(V, min(V, 2048), replace=False)
     ref = oracle.dslash_sites(U, psi, mass, sites)
     parity = float(np.linalg.norm(out[sites] - ref) / np.linalg.norm(ref))
-    tol = 1e-13 if args.prec == "fp64" else 1e-6
+    tol = {"fp64": 1e-13, "fp32": 1e-6, "fp16": 2e-3}[args.prec]
     del g, src, dst
 
     variants = {}
     if not args.no_variants:
-        for p, c in (("fp64", True), ("fp32", False), ("fp32", True)):
+        for p, c in (("fp64", False), ("fp64", True), ("fp32", False), ("fp32", True),
+                     ("fp16", False), ("fp16", True)):
             if (p, c) == (args.prec, args.c12):
                 continue
             gv, sv, dv, msv, _ = measure(p, c, max(20, args.steps // 4), 5)
@@ -353,7 +367,11 @@ def main(argv=None):
     multi = None
     if not args.no_multi:
         print("[bench] multi-RHS 24^3x48 x12", file=sys.stderr, flush=True)
-        multi = bench_multi(torch, w, li, DeviceGauge)
+        mdims = (24, 24, 24, 48)
+        minputs = (li.near_unity_gauge(mdims, li.seed_gauge(3), 0.3),
+                   li.gaussian_spinors(mdims, [li.seed_spinor(3, k) for k in range(12)]))
+        multi = {p: bench_multi(torch, w, li, DeviceGauge, p, inputs=minputs) for p in ("fp32", "fp16")}
+        del minputs
     cg = None
     if not args.no_cg:
         print("[bench] CG 24^4", file=sys.stderr, flush=True)
@@ -393,7 +411,7 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "f32",
+        "dtype": "f64" if args.prec == "fp64" else "f32",  # FP16 storage computes in FP32
         "data": "synthetic (seeded random SU(3) links, Gaussian spinor)",
         "config": {"workload": workload, "dims": list(dims), "prec": args.prec,
                    "links": "12-real" if args.c12 else "full", "mass": mass,
