@@ -153,18 +153,24 @@ def bench_multi(torch, w, li, DeviceGauge, prec="fp32", steps=50, warmup=5, inpu
 def bench_cg(torch, w, li, DeviceGauge, reps=3):
     """Solves of D^dag D x = b on 24^4, m = 0.05, near-unity links, to a true
     residual of 1e-10: plain FP64 CG against FP32 or FP16-storage inner
-    iterations with FP64 reliable updates."""
-    dims, m = (24, 24, 24, 24), 0.05
-    U = li.near_unity_gauge(dims, li.seed_gauge(4), 0.3)
-    b = li.gaussian_spinor(dims, li.seed_spinor(4))
-    ghi = DeviceGauge(U, w.WD_FP64)
-    glo = {w.WD_FP64: ghi, w.WD_FP32: DeviceGauge(U, w.WD_FP32), w.WD_FP16: DeviceGauge(U, w.WD_FP16)}
-    bd = ghi.pack(b)
-    x = ghi.spinor(1)
-    out = {"workload": "cg_normal_24x24x24x24_m0.05", "tol": 1e-10, "gauge": "near-unity eps=0.3"}
-    for name, inner in (("fp64", w.WD_FP64), ("mixed_fp32", w.WD_FP32), ("mixed_fp16", w.WD_FP16)):
+    iterations with FP64 reliable updates, eager and with chunks of iterations
+    replayed as HIP graphs; and the same eager/graph pair on an 8^4 lattice,
+    where launch overhead dominates."""
+    m = 0.05
+
+    def setup(dims):
+        U = li.near_unity_gauge(dims, li.seed_gauge(4), 0.3)
+        b = li.gaussian_spinor(dims, li.seed_spinor(4))
+        ghi = DeviceGauge(U, w.WD_FP64)
+        glo = {w.WD_FP64: ghi, w.WD_FP32: DeviceGauge(U, w.WD_FP32),
+               w.WD_FP16: DeviceGauge(U, w.WD_FP16)}
+        return ghi, glo, ghi.pack(b), ghi.spinor(1)
+
+    def run(dims, lat, inner, use_graph):
+        ghi, glo, bd, x = lat
         ws = torch.empty(w.cg_workspace_bytes(dims, 1, inner), dtype=torch.uint8, device="cuda")
-        params = dict(tol=1e-10, max_iter=20000, inner=inner, delta=0.1, check_every=8, x0_given=0)
+        params = dict(tol=1e-10, max_iter=20000, inner=inner, delta=0.1, check_every=8, x0_given=0,
+                      use_graph=use_graph)
         gl = glo[inner].handle
         w.cg_solve_normal(ghi.handle, gl, [m], 1, bd, x, params, ws)  # warm-up
         torch.cuda.synchronize()
@@ -173,12 +179,26 @@ def bench_cg(torch, w, li, DeviceGauge, reps=3):
             rc, st = w.cg_solve_normal(ghi.handle, gl, [m], 1, bd, x, params, ws)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
-        out[name] = {"status": rc, "solves_per_s": round(1.0 / dt, 2), "ms_per_solve": round(dt * 1e3, 2),
-                     "iters": st[0]["iters"], "reliable_updates": st[0]["reliable_updates"],
-                     "true_rel_residual": st[0]["true_rel_residual"]}
-        del ws
-    out["mixed_fp32_speedup"] = round(out["fp64"]["ms_per_solve"] / out["mixed_fp32"]["ms_per_solve"], 3)
-    out["mixed_fp16_speedup"] = round(out["fp64"]["ms_per_solve"] / out["mixed_fp16"]["ms_per_solve"], 3)
+        return {"status": rc, "solves_per_s": round(1.0 / dt, 2), "ms_per_solve": round(dt * 1e3, 3),
+                "iters": st[0]["iters"], "reliable_updates": st[0]["reliable_updates"],
+                "true_rel_residual": st[0]["true_rel_residual"]}
+
+    dims = (24, 24, 24, 24)
+    lat = setup(dims)
+    out = {"workload": "cg_normal_24x24x24x24_m0.05", "tol": 1e-10, "gauge": "near-unity eps=0.3",
+           "check_every": 8}
+    for name, inner, graph in (("fp64", w.WD_FP64, 0), ("mixed_fp32", w.WD_FP32, 0),
+                               ("mixed_fp16", w.WD_FP16, 0), ("fp64_graph", w.WD_FP64, 1),
+                               ("mixed_fp32_graph", w.WD_FP32, 1), ("mixed_fp16_graph", w.WD_FP16, 1)):
+        out[name] = run(dims, lat, inner, graph)
+    base = out["fp64"]["ms_per_solve"]
+    for name in ("mixed_fp32", "mixed_fp16", "fp64_graph", "mixed_fp32_graph", "mixed_fp16_graph"):
+        out[name]["speedup_vs_fp64"] = round(base / out[name]["ms_per_solve"], 3)
+    del lat
+    small = (8, 8, 8, 8)
+    lat = setup(small)
+    out["small_8x8x8x8"] = {name: run(small, lat, inner, graph) for name, inner, graph in
+                            (("mixed_fp32", w.WD_FP32, 0), ("mixed_fp32_graph", w.WD_FP32, 1))}
     return out
 
 

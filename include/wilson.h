@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define WD_ABI_VERSION 1
+#define WD_ABI_VERSION 2
 
 #if defined(__GNUC__)
 #define WD_API __attribute__((visibility("default")))
@@ -183,6 +183,9 @@ typedef struct wd_cg_params {
   double delta;        /* reliable-update threshold in (0, 1); used with mixed precision */
   int32_t check_every; /* >= 1; iterations between host checks of the residual */
   int32_t x0_given;    /* nonzero: start from the contents of x_dev, else x0 = 0 */
+  int32_t use_graph;   /* nonzero: each run of check_every iterations is captured once as a
+                          HIP graph (per set of unconverged right-hand sides) and replayed, on a
+                          stream of the library's own ordered after `stream`; same results */
 } wd_cg_params;
 
 typedef struct wd_cg_stats {

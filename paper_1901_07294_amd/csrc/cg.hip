@@ -22,6 +22,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <map>
+#include <memory>
 #include <vector>
 
 #include "cg_engine.h"
@@ -161,13 +163,90 @@ RhsSet set_of(const std::vector<int>& ks) {
   return s;
 }
 
+// Chunks of CG iterations captured as HIP graphs and replayed: one graph per
+// (set of active right-hand sides, chunk length). The scalars never leave the
+// device inside a chunk, so a replay needs no host work between iterations.
+class ChunkGraphs {
+ public:
+  explicit ChunkGraphs(hipStream_t st) : st_(st) {}
+  ~ChunkGraphs() {
+    for (auto& e : execs_) (void)hipGraphExecDestroy(e.second);
+  }
+  ChunkGraphs(const ChunkGraphs&) = delete;
+  ChunkGraphs& operator=(const ChunkGraphs&) = delete;
+
+  // n iterations of eng on set, captured the first time (set, n) is seen
+  int run(CgEngine& eng, const RhsSet& set, int n) {
+    std::vector<int> key(set.idx, set.idx + set.n);
+    key.push_back(-n);
+    auto it = execs_.find(key);
+    if (it == execs_.end()) {
+      hipError_t e = hipStreamBeginCapture(st_, hipStreamCaptureModeRelaxed);
+      if (e != hipSuccess) return set_error(WD_ERR_DEVICE, "cg: graph capture: %s", hipGetErrorString(e));
+      int rc = WD_OK;
+      for (int i = 0; i < n && rc == WD_OK; ++i) rc = eng.iterate(set);
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(st_, &graph);
+      hipGraphExec_t exec = nullptr;
+      if (rc == WD_OK && e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (graph != nullptr) (void)hipGraphDestroy(graph);
+      if (rc != WD_OK) return rc;
+      if (e != hipSuccess) return set_error(WD_ERR_DEVICE, "cg: graph: %s", hipGetErrorString(e));
+      it = execs_.emplace(std::move(key), exec).first;
+    }
+    const hipError_t e = hipGraphLaunch(it->second, st_);
+    return e == hipSuccess ? WD_OK : set_error(WD_ERR_DEVICE, "cg: graph launch: %s", hipGetErrorString(e));
+  }
+
+ private:
+  hipStream_t st_;
+  std::map<std::vector<int>, hipGraphExec_t> execs_;
+};
+
+// A stream of the library's own for graph capture (the caller's may be the
+// null stream, which cannot be captured), ordered after the caller's work.
+class OwnStream {
+ public:
+  explicit OwnStream(hipStream_t after) {
+    if (hipStreamCreateWithFlags(&st_, hipStreamNonBlocking) != hipSuccess) { st_ = nullptr; return; }
+    if (hipEventCreateWithFlags(&ev_, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ev_, after) != hipSuccess || hipStreamWaitEvent(st_, ev_, 0) != hipSuccess)
+      ok_ = false;
+  }
+  ~OwnStream() {
+    if (st_ != nullptr) {
+      (void)hipStreamSynchronize(st_);
+      (void)hipStreamDestroy(st_);
+    }
+    if (ev_ != nullptr) (void)hipEventDestroy(ev_);
+  }
+  OwnStream(const OwnStream&) = delete;
+  OwnStream& operator=(const OwnStream&) = delete;
+  bool ok() const { return st_ != nullptr && ok_; }
+  hipStream_t get() const { return st_; }
+
+ private:
+  hipStream_t st_ = nullptr;
+  hipEvent_t ev_ = nullptr;
+  bool ok_ = true;
+};
+
 // The synchronous solver: all right-hand sides start together; every
 // check_every iterations the host reads the scalars, recomputes the true
-// residual of those that need it, and drops the finished ones.
+// residual of those that need it, and drops the finished ones. With
+// use_graph, each chunk of iterations between two reads is a graph replay.
 int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, int nrhs,
                const void* b, void* x, const wd_cg_params& prm, wd_cg_stats* stats, void* ws,
-               hipStream_t st) {
+               hipStream_t caller) {
   const auto t_start = std::chrono::steady_clock::now();
+  std::unique_ptr<OwnStream> own;
+  if (prm.use_graph) {
+    own = std::make_unique<OwnStream>(caller);
+    if (!own->ok()) return set_error(WD_ERR_DEVICE, "cg: cannot create a stream for graph capture");
+  }
+  const hipStream_t st = own ? own->get() : caller;
+  std::unique_ptr<ChunkGraphs> graphs;
+  if (own) graphs = std::make_unique<ChunkGraphs>(st);
   CgEngine eng(ghi, glo, prm.inner, nrhs, b, x, ws, st);
   for (int k = 0; k < nrhs; ++k) eng.set_mass(k, masses[k]);
   std::vector<double> hs(static_cast<size_t>(nrhs) * kScalars, 0.0);
@@ -194,12 +273,18 @@ int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, i
   }
   int it = 0;
   while (rc == WD_OK && !active.empty() && it < prm.max_iter) {
-    rc = eng.iterate(set_of(active));
+    // iterations up to the next check (a multiple of check_every, or max_iter)
+    const int n = std::min(prm.check_every - it % prm.check_every, prm.max_iter - it);
+    const RhsSet set = set_of(active);
+    if (graphs) {
+      rc = graphs->run(eng, set, n);
+    } else {
+      for (int i = 0; i < n && rc == WD_OK; ++i) rc = eng.iterate(set);
+    }
     if (rc != WD_OK) break;
-    ++it;
+    it += n;
     for (int k : active) iters[k] = it;
     const bool at_max = it >= prm.max_iter;
-    if (it % prm.check_every != 0 && !at_max) continue;
     if ((rc = read()) != WD_OK) break;
     std::vector<int> refresh, keep;
     for (int k : active) {

@@ -36,6 +36,8 @@ WD_FP16 = 2
 
 WD_FLAG_GAMMA5 = 1
 
+ABI_VERSION = 2  # the structures below match this version of include/wilson.h
+
 STATUS_NAMES = {v: k for k, v in dict(globals()).items()
                 if k.startswith("WD_ERR_") or k in ("WD_OK", "WD_PENDING")}
 
@@ -43,7 +45,7 @@ STATUS_NAMES = {v: k for k, v in dict(globals()).items()
 class wd_cg_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("inner", ctypes.c_int32),
                 ("delta", ctypes.c_double), ("check_every", ctypes.c_int32),
-                ("x0_given", ctypes.c_int32)]
+                ("x0_given", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 class wd_cg_stats(ctypes.Structure):
@@ -132,6 +134,9 @@ def _load(path=_LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    if lib.wd_abi_version() != ABI_VERSION:
+        raise ImportError(f"{path} implements ABI version {lib.wd_abi_version()}, "
+                          f"this binding expects {ABI_VERSION}; rebuild the library")
     return lib
 
 

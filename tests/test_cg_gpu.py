@@ -31,7 +31,8 @@ def true_rel_residual(U, m, b, x):
     return float(np.linalg.norm(r) / np.linalg.norm(b))
 
 
-def solve(U, masses, bs, inner, tol=1e-10, max_iter=20000, delta=0.1, check_every=4, x0=None):
+def solve(U, masses, bs, inner, tol=1e-10, max_iter=20000, delta=0.1, check_every=4, x0=None,
+          use_graph=0):
     """Solve through the C ABI; bs: [nrhs, T, Z, Y, X, 4, 3]. Returns (rc, xs, stats)."""
     nrhs = len(masses)
     ghi = DeviceGauge(U, w.WD_FP64)
@@ -40,7 +41,7 @@ def solve(U, masses, bs, inner, tol=1e-10, max_iter=20000, delta=0.1, check_ever
     x = ghi.pack(x0, nrhs=nrhs) if x0 is not None else ghi.spinor(nrhs)
     ws = torch.empty(w.cg_workspace_bytes(ghi.dims, nrhs, inner), dtype=torch.uint8, device="cuda")
     params = dict(tol=tol, max_iter=max_iter, inner=inner, delta=delta, check_every=check_every,
-                  x0_given=int(x0 is not None))
+                  x0_given=int(x0 is not None), use_graph=use_graph)
     rc, stats = w.cg_solve_normal(ghi.handle, glo.handle if glo else None, masses, nrhs, b, x,
                                   params, ws)
     xs = ghi.unpack(x, nrhs=nrhs)
@@ -116,6 +117,34 @@ def test_cg_multi_rhs_equals_alone():
             assert true_rel_residual(U, masses[k], bs[k], xs[k]) <= 1e-10
         # heavier masses converge in fewer iterations
         assert stats[2]["iters"] < stats[0]["iters"]
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "fp16"])
+def test_cg_graph_replay_equals_eager(inner):
+    """Chunks of iterations captured as HIP graphs and replayed give the eager
+    solver's bits. The run uses several graphs (the set of unconverged
+    right-hand sides shrinks), each replayed many times with scalar reads and
+    eager reliable updates between replays, and a short last chunk."""
+    dims = (8, 8, 4, 4)
+    U = li.near_unity_gauge(dims, 77, 0.3)
+    bs = li.gaussian_spinors(dims, [81, 82, 83])
+    masses = [0.05, 0.2, 0.5]
+    rc_e, x_e, st_e, _ = solve(U, masses, bs, INNER[inner], check_every=3)
+    rc_g, x_g, st_g, _ = solve(U, masses, bs, INNER[inner], check_every=3, use_graph=1)
+    assert rc_e == rc_g == w.WD_OK
+    assert np.array_equal(x_e, x_g)
+    for k in range(3):
+        assert st_e[k]["iters"] == st_g[k]["iters"]
+        assert st_e[k]["reliable_updates"] == st_g[k]["reliable_updates"]
+        assert true_rel_residual(U, masses[k], bs[k], x_g[k]) <= 1e-10
+    assert len({s["iters"] for s in st_g}) == 3  # three different active sets
+    # max_iter not a multiple of check_every: a last chunk of 1 iteration
+    rc_e, x_e, st_e, _ = solve(U, [0.05], bs[:1], INNER[inner], max_iter=7, check_every=3)
+    rc_g, x_g, st_g, _ = solve(U, [0.05], bs[:1], INNER[inner], max_iter=7, check_every=3,
+                               use_graph=1)
+    assert rc_e == rc_g == w.WD_ERR_NOT_CONVERGED
+    assert st_e[0]["iters"] == st_g[0]["iters"] == 7
+    assert np.array_equal(x_e, x_g)
 
 
 def test_cg_start_from_solution_and_zero_rhs():
