@@ -162,6 +162,53 @@ WD_API int dslash_apply_multi(const wd_gauge* g, const double* masses_host, int3
                               hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Autotuner of the dslash launch (not from the paper: a search over launch
+ * choices of the operator of eq. (1), Sec. II-A, on this device).
+ *
+ * Only choices that leave every site's arithmetic unchanged are searched: t
+ * steps per workgroup, right-hand sides per workgroup and the run length of
+ * tiles per XCD of the t-marching kernel. A candidate is eligible only if its
+ * output is bit-identical to the default choice's; the fastest eligible one
+ * is kept in a process-wide cache keyed by (dims, prec, compress12, nrhs) and
+ * used by every later dslash_apply / dslash_apply_multi / CG launch of that
+ * key. The cache is empty at load time (defaults apply) and thread-safe.
+ * ------------------------------------------------------------------------ */
+
+typedef struct wd_tune_result {
+  int32_t candidates;  /* launch choices timed (0: this lattice uses the one-site-per-lane kernel) */
+  int32_t eligible;    /* of those, bit-identical to the default choice */
+  int32_t tb, gw, group;  /* the choice kept: t steps and right-hand sides per workgroup, XCD run */
+  int32_t reserved;
+  double default_us;   /* average time per launch of the default choice */
+  double best_us;      /* ... and of the choice kept */
+} wd_tune_result;
+
+/* Times every candidate for g's lattice with nrhs right-hand sides (masses
+ * 0.1) over reps launches each and registers the fastest eligible one. in_dev
+ * holds nrhs packed spinors of g's precision; out_dev and ref_dev are scratch
+ * buffers of the same size, overwritten. Synchronous on stream; allocates a
+ * few bytes of device memory for the comparison. Errors: WD_ERR_INVALID_ARG
+ * (buffers, reps outside 1..1000), WD_ERR_UNSUPPORTED (nrhs), WD_ERR_DEVICE. */
+WD_API int wd_tune_dslash(const wd_gauge* g, int32_t nrhs, const void* in_dev, void* out_dev,
+                          void* ref_dev, int32_t reps, hipStream_t stream, wd_tune_result* result);
+
+/* 1 and choice = {tb, gw, group} if a choice is registered for the key, 0 if
+ * not, negative for invalid arguments. */
+WD_API int wd_tune_lookup(const int32_t dims[4], int32_t prec, int32_t compress12, int32_t nrhs,
+                          int32_t choice[3]);
+
+/* Forgets every registered choice. */
+WD_API int wd_tune_reset(void);
+
+/* Writes the registered choices to a text file (one line per key). */
+WD_API int wd_tune_save(const char* path);
+
+/* Adds the choices of a file written by wd_tune_save. Every line is checked
+ * against its lattice (bounds, lanes, LDS); a file with any invalid line is
+ * rejected whole with WD_ERR_INVALID_ARG and registers nothing. */
+WD_API int wd_tune_load(const char* path);
+
+/* ------------------------------------------------------------------------
  * Conjugate gradient on the normal equations D^dag D x = b.
  *
  * Sec. II-A of the paper names iterative solvers such as conjugate gradient

@@ -391,9 +391,18 @@ hipError_t launch_site(const void* in, void* out, const void* links, const Geo& 
   return hipGetLastError();
 }
 
+// Applies a tuning choice to the default parameters.
+MarchParams with_tuning(MarchParams p, const MarchTuning& t) {
+  p.tb = t.tb;
+  p.gw = t.gw;
+  p.group = t.group;
+  return p;
+}
+
 template <typename T, bool C12>
-hipError_t launch_typed(const void* in, void* out, const void* links, const Geo& geo,
-                        const double* masses, int nrhs, const int* fields, int g5, hipStream_t st) {
+hipError_t launch_typed(const wd_gauge* g, const void* in, void* out, const Geo& geo,
+                        const double* masses, int nrhs, const int* fields, int g5,
+                        const MarchTuning* force, hipStream_t st) {
   using R = typename Packed<T>::R;
   Diag<R> diag{};
   for (int k = 0; k < nrhs; ++k) {
@@ -401,38 +410,109 @@ hipError_t launch_typed(const void* in, void* out, const void* links, const Geo&
     diag.idx[k] = fields ? fields[k] : k;
   }
   const long stride = spinor_units<T>(geo.V);  // 16-B elements per field
-  const MarchParams p = march_params(geo, sizeof(R), nrhs);
-  if (WD_DSLASH_KERNEL == 0 && p.ny > 0)
-    return launch_march<T, C12>(in, out, links, geo, diag, stride, g5, p, st);
-  return launch_site<T, C12>(in, out, links, geo, diag, nrhs, stride, g5, st);
+  MarchParams p = march_params(geo, sizeof(R), nrhs);
+  if (WD_DSLASH_KERNEL == 0 && p.ny > 0) {
+    MarchTuning t;
+    if (force != nullptr) p = with_tuning(p, *force);
+    else if (tuned_lookup(g->dims, g->prec, g->c12, nrhs, &t)) p = with_tuning(p, t);
+    return launch_march<T, C12>(in, out, g->links, geo, diag, stride, g5, p, st);
+  }
+  return launch_site<T, C12>(in, out, g->links, geo, diag, nrhs, stride, g5, st);
 }
 
 template <typename T>
 hipError_t launch_prec(const wd_gauge* g, const void* in, void* out, const Geo& geo,
-                       const double* masses, int nrhs, const int* fields, int g5, hipStream_t st) {
-  return g->c12 ? launch_typed<T, true>(in, out, g->links, geo, masses, nrhs, fields, g5, st)
-                : launch_typed<T, false>(in, out, g->links, geo, masses, nrhs, fields, g5, st);
+                       const double* masses, int nrhs, const int* fields, int g5,
+                       const MarchTuning* force, hipStream_t st) {
+  return g->c12 ? launch_typed<T, true>(g, in, out, geo, masses, nrhs, fields, g5, force, st)
+                : launch_typed<T, false>(g, in, out, geo, masses, nrhs, fields, g5, force, st);
 }
 
-}  // namespace
-
-hipError_t launch_dslash_multi(const wd_gauge* g, const double* masses, int nrhs, const int* fields,
-                               const void* in, void* out, int flags, hipStream_t st) {
+hipError_t launch_any(const wd_gauge* g, const double* masses, int nrhs, const int* fields,
+                      const void* in, void* out, int flags, const MarchTuning* force, hipStream_t st) {
   if (nrhs < 1) return hipSuccess;
   if (nrhs > kMaxMultiRhs) return hipErrorInvalidValue;
   const Geo geo = make_geo(g->dims);
   const int g5 = (flags & WD_FLAG_GAMMA5) ? 1 : 0;
   switch (g->prec) {
-    case WD_FP64: return launch_prec<double>(g, in, out, geo, masses, nrhs, fields, g5, st);
-    case WD_FP32: return launch_prec<float>(g, in, out, geo, masses, nrhs, fields, g5, st);
-    case WD_FP16: return launch_prec<_Float16>(g, in, out, geo, masses, nrhs, fields, g5, st);
+    case WD_FP64: return launch_prec<double>(g, in, out, geo, masses, nrhs, fields, g5, force, st);
+    case WD_FP32: return launch_prec<float>(g, in, out, geo, masses, nrhs, fields, g5, force, st);
+    case WD_FP16: return launch_prec<_Float16>(g, in, out, geo, masses, nrhs, fields, g5, force, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+size_t real_bytes_of(int prec) { return prec == WD_FP64 ? 8 : 4; }
+
+}  // namespace
+
+hipError_t launch_dslash_multi(const wd_gauge* g, const double* masses, int nrhs, const int* fields,
+                               const void* in, void* out, int flags, hipStream_t st) {
+  return launch_any(g, masses, nrhs, fields, in, out, flags, nullptr, st);
 }
 
 hipError_t launch_dslash(const wd_gauge* g, double mass, const void* in, void* out, int flags,
                          hipStream_t st) {
   return launch_dslash_multi(g, &mass, 1, nullptr, in, out, flags, st);
+}
+
+hipError_t launch_dslash_tuned(const wd_gauge* g, const double* masses, int nrhs, const void* in,
+                               void* out, int flags, const MarchTuning& t, hipStream_t st) {
+  return launch_any(g, masses, nrhs, nullptr, in, out, flags, &t, st);
+}
+
+bool march_default(const int32_t dims[4], int prec, int nrhs, MarchTuning* t) {
+  if (WD_DSLASH_KERNEL != 0) return false;
+  const MarchParams p = march_params(make_geo(dims), real_bytes_of(prec), nrhs);
+  if (p.ny == 0) return false;
+  *t = MarchTuning{p.tb, p.gw, p.group};
+  return true;
+}
+
+bool march_tuning_valid(const int32_t dims[4], int prec, int nrhs, const MarchTuning& t) {
+  const Geo geo = make_geo(dims);
+  const size_t real = real_bytes_of(prec);
+  const MarchParams p = march_params(geo, real, nrhs);
+  if (WD_DSLASH_KERNEL != 0 || p.ny == 0 || nrhs < 1 || nrhs > kMaxMultiRhs) return false;
+  if (t.tb < 1 || t.tb > geo.T || t.group < 0) return false;
+  if (t.gw < 1 || nrhs % t.gw != 0) return false;
+  const int n = geo.X * p.ny;
+  if (t.gw > 1) {  // several right-hand sides per workgroup: FP32 arithmetic only
+    if (real != 4 || t.gw * n > kMarchMultiThreads) return false;
+  }
+  if (static_cast<size_t>(t.gw) * march_lds_bytes(n, real) > kLdsBytes) return false;
+  const long nb = static_cast<long>(nrhs / t.gw) * p.ytiles * geo.Z * ((geo.T + t.tb - 1) / t.tb);
+  return nb >= 1 && nb <= 0x7fffffffL;
+}
+
+void march_candidates(const int32_t dims[4], int prec, int nrhs, MarchTuning* out, int* n, int cap) {
+  *n = 0;
+  MarchTuning d;
+  if (!march_default(dims, prec, nrhs, &d) || cap < 1) return;
+  out[(*n)++] = d;
+  const Geo geo = make_geo(dims);
+  const MarchParams p = march_params(geo, real_bytes_of(prec), nrhs);
+  // t steps per workgroup: the distinct ceil(T / nt) for nt workgroups along t
+  int tbs[64];
+  int ntb = 0;
+  for (int nt = 1; nt <= geo.T && ntb < 64; ++nt) {
+    const int tb = (geo.T + nt - 1) / nt;
+    if (tb < 2 && nt > 1) break;
+    if (ntb == 0 || tbs[ntb - 1] != tb) tbs[ntb++] = tb;
+  }
+  for (int gw = 1; gw <= nrhs; ++gw) {
+    if (nrhs % gw != 0) continue;
+    for (int i = 0; i < ntb; ++i) {
+      const long nb = static_cast<long>(nrhs / gw) * p.ytiles * geo.Z * ((geo.T + tbs[i] - 1) / tbs[i]);
+      const int groups[2] = {0, nb % kNumXcd == 0 ? static_cast<int>(nb / kNumXcd) : 0};
+      for (int j = 0; j < (groups[1] > 0 ? 2 : 1); ++j) {
+        const MarchTuning t{tbs[i], gw, groups[j]};
+        if (!march_tuning_valid(dims, prec, nrhs, t)) continue;
+        if (t.tb == d.tb && t.gw == d.gw && t.group == d.group) continue;
+        if (*n < cap) out[(*n)++] = t;
+      }
+    }
+  }
 }
 
 }  // namespace wd

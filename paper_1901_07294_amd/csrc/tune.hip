@@ -1,0 +1,273 @@
+// Autotuner of the t-marching dslash launch.
+//
+// Only choices that leave every site's arithmetic unchanged are tuned (t steps
+// per workgroup, right-hand sides per workgroup, XCD run length of tiles), so
+// a candidate is eligible only if its output is bit-identical to the default
+// choice's output on the same input. The fastest eligible choice is kept in a
+// process-wide cache keyed by lattice, precision, link format and number of
+// right-hand sides, which every later launch of that key uses, and which can
+// be saved to and loaded from a text file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "fields.h"
+#include "wd_internal.h"
+
+namespace wd {
+namespace {
+
+using Key = std::tuple<int, int, int, int, int, int, int>;  // X, Y, Z, T, prec, c12, nrhs
+
+std::mutex g_mu;
+std::map<Key, MarchTuning> g_cache;
+std::atomic<bool> g_any{false};
+
+Key key_of(const int32_t dims[4], int prec, int c12, int nrhs) {
+  return Key{dims[0], dims[1], dims[2], dims[3], prec, c12 ? 1 : 0, nrhs};
+}
+
+constexpr int kMaxCandidates = 256;
+constexpr int kCompareThreads = 256;
+
+// Number of 16-byte words in which a and b differ, added to *count.
+__global__ __launch_bounds__(kCompareThreads) void count_diff_kernel(const uint4* __restrict__ a,
+                                                                     const uint4* __restrict__ b,
+                                                                     long n, int* __restrict__ count) {
+  int local = 0;
+  for (long i = static_cast<long>(blockIdx.x) * kCompareThreads + threadIdx.x; i < n;
+       i += static_cast<long>(gridDim.x) * kCompareThreads) {
+    const uint4 x = a[i];
+    const uint4 y = b[i];
+    local += (x.x != y.x) | (x.y != y.y) | (x.z != y.z) | (x.w != y.w);
+  }
+  if (local > 0) atomicAdd(count, local);
+}
+
+const char* kHeader = "# wilson dslash launch tuning v1: X Y Z T prec c12 nrhs tb gw group";
+
+// Device resources of one tuning run, released on every path.
+struct TuneScratch {
+  int* flags = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~TuneScratch() {
+    if (flags != nullptr) (void)hipFree(flags);
+    if (e0 != nullptr) (void)hipEventDestroy(e0);
+    if (e1 != nullptr) (void)hipEventDestroy(e1);
+  }
+};
+
+}  // namespace
+
+bool tuned_lookup(const int32_t dims[4], int prec, int c12, int nrhs, MarchTuning* t) {
+  if (!g_any.load(std::memory_order_acquire)) return false;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const auto it = g_cache.find(key_of(dims, prec, c12, nrhs));
+  if (it == g_cache.end()) return false;
+  *t = it->second;
+  return true;
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+int wd_tune_dslash(const wd_gauge* g, int32_t nrhs, const void* in_dev, void* out_dev, void* ref_dev,
+                   int32_t reps, hipStream_t stream, wd_tune_result* result) {
+  try {
+    clear_error();
+    int rc = check_gauge(g);
+    if (rc != WD_OK) return rc;
+    if (nrhs < 1 || nrhs > kMaxMultiRhs)
+      return set_error(WD_ERR_UNSUPPORTED, "nrhs %d outside 1..%d", nrhs, kMaxMultiRhs);
+    if (reps < 1 || reps > 1000) return set_error(WD_ERR_INVALID_ARG, "reps %d outside 1..1000", reps);
+    if (result == nullptr) return set_error(WD_ERR_INVALID_ARG, "result is NULL");
+    const size_t bytes = static_cast<size_t>(packed_sites(g->V)) * nrhs * spinor_site_bytes(g->prec);
+    if ((rc = check_device_range(in_dev, bytes, "in_dev")) != WD_OK) return rc;
+    if ((rc = check_device_range(out_dev, bytes, "out_dev")) != WD_OK) return rc;
+    if ((rc = check_device_range(ref_dev, bytes, "ref_dev")) != WD_OK) return rc;
+    if (overlaps(in_dev, bytes, out_dev, bytes) || overlaps(in_dev, bytes, ref_dev, bytes) ||
+        overlaps(out_dev, bytes, ref_dev, bytes))
+      return set_error(WD_ERR_INVALID_ARG, "in_dev, out_dev and ref_dev must not overlap");
+    std::memset(result, 0, sizeof(*result));
+
+    MarchTuning cand[kMaxCandidates];
+    int nc = 0;
+    march_candidates(g->dims, g->prec, nrhs, cand, &nc, kMaxCandidates);
+    if (nc == 0) return WD_OK;  // the one-site-per-lane kernel runs: nothing to tune
+
+    double masses[kMaxMultiRhs];
+    for (int k = 0; k < nrhs; ++k) masses[k] = 0.1;
+    TuneScratch sc;
+    if (hipMalloc(&sc.flags, sizeof(int) * nc) != hipSuccess || hipEventCreate(&sc.e0) != hipSuccess ||
+        hipEventCreate(&sc.e1) != hipSuccess)
+      return set_error(WD_ERR_NOMEM, "tuner: device scratch allocation failed");
+    // zeroed outputs: the padding sites, which no launch writes, compare equal
+    if (hipMemsetAsync(sc.flags, 0, sizeof(int) * nc, stream) != hipSuccess ||
+        hipMemsetAsync(out_dev, 0, bytes, stream) != hipSuccess ||
+        hipMemsetAsync(ref_dev, 0, bytes, stream) != hipSuccess)
+      return set_error(WD_ERR_DEVICE, "tuner: clearing the outputs failed");
+    if ((rc = launch_status(launch_dslash_tuned(g, masses, nrhs, in_dev, ref_dev, 0, cand[0], stream),
+                            "tuner: reference launch")) != WD_OK)
+      return rc;
+    const long words = static_cast<long>(bytes / 16);
+    const unsigned cmp_blocks = static_cast<unsigned>(std::min<long>((words + 4095) / 4096 + 1, 2048));
+    std::vector<double> us(nc, 0.0);
+    for (int i = 0; i < nc; ++i) {
+      if ((rc = launch_status(launch_dslash_tuned(g, masses, nrhs, in_dev, out_dev, 0, cand[i], stream),
+                              "tuner: candidate")) != WD_OK)
+        return rc;
+      count_diff_kernel<<<cmp_blocks, kCompareThreads, 0, stream>>>(
+          static_cast<const uint4*>(out_dev), static_cast<const uint4*>(ref_dev), words, sc.flags + i);
+      if ((rc = launch_status(hipGetLastError(), "tuner: compare")) != WD_OK) return rc;
+      if (hipEventRecord(sc.e0, stream) != hipSuccess) return set_error(WD_ERR_DEVICE, "tuner: event");
+      for (int r = 0; r < reps; ++r)
+        if ((rc = launch_status(launch_dslash_tuned(g, masses, nrhs, in_dev, out_dev, 0, cand[i], stream),
+                                "tuner: timed launch")) != WD_OK)
+          return rc;
+      float ms = 0.0f;
+      if (hipEventRecord(sc.e1, stream) != hipSuccess || hipEventSynchronize(sc.e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, sc.e0, sc.e1) != hipSuccess)
+        return set_error(WD_ERR_DEVICE, "tuner: timing failed");
+      us[i] = 1e3 * ms / reps;
+    }
+    std::vector<int> diff(nc, 0);
+    if (hipMemcpyAsync(diff.data(), sc.flags, sizeof(int) * nc, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return set_error(WD_ERR_DEVICE, "tuner: reading the comparisons failed");
+    if (diff[0] != 0)
+      return set_error(WD_ERR_INTERNAL, "tuner: the default launch is not reproducible");
+    int best = 0, eligible = 0;
+    for (int i = 0; i < nc; ++i) {
+      if (diff[i] != 0) continue;
+      ++eligible;
+      if (us[i] < us[best]) best = i;
+    }
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_cache[key_of(g->dims, g->prec, g->c12, nrhs)] = cand[best];
+      g_any.store(true, std::memory_order_release);
+    }
+    result->candidates = nc;
+    result->eligible = eligible;
+    result->tb = cand[best].tb;
+    result->gw = cand[best].gw;
+    result->group = cand[best].group;
+    result->default_us = us[0];
+    result->best_us = us[best];
+    return WD_OK;
+  } catch (...) {
+    return set_error(WD_ERR_INTERNAL, "unexpected exception in wd_tune_dslash");
+  }
+}
+
+int wd_tune_lookup(const int32_t dims[4], int32_t prec, int32_t compress12, int32_t nrhs,
+                   int32_t choice[3]) {
+  clear_error();
+  long V = 0;
+  int rc = check_dims(dims, &V);
+  if (rc != WD_OK) return rc;
+  if ((rc = check_prec(prec)) != WD_OK) return rc;
+  if (choice == nullptr) return set_error(WD_ERR_INVALID_ARG, "choice is NULL");
+  MarchTuning t;
+  if (!tuned_lookup(dims, prec, compress12 ? 1 : 0, nrhs, &t)) return 0;
+  choice[0] = t.tb;
+  choice[1] = t.gw;
+  choice[2] = t.group;
+  return 1;
+}
+
+int wd_tune_reset(void) {
+  clear_error();
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache.clear();
+  g_any.store(false, std::memory_order_release);
+  return WD_OK;
+}
+
+int wd_tune_save(const char* path) {
+  try {
+    clear_error();
+    if (path == nullptr) return set_error(WD_ERR_INVALID_ARG, "path is NULL");
+    std::map<Key, MarchTuning> snap;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      snap = g_cache;
+    }
+    FILE* f = std::fopen(path, "w");
+    if (f == nullptr) return set_error(WD_ERR_INVALID_ARG, "cannot open %s for writing", path);
+    bool ok = std::fprintf(f, "%s\n", kHeader) > 0;
+    for (const auto& [k, t] : snap)
+      ok = ok && std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k),
+                              std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k),
+                              std::get<6>(k), t.tb, t.gw, t.group) > 0;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? WD_OK : set_error(WD_ERR_INVALID_ARG, "writing %s failed", path);
+  } catch (...) {
+    return set_error(WD_ERR_INTERNAL, "unexpected exception in wd_tune_save");
+  }
+}
+
+int wd_tune_load(const char* path) {
+  try {
+    clear_error();
+    if (path == nullptr) return set_error(WD_ERR_INVALID_ARG, "path is NULL");
+    FILE* f = std::fopen(path, "r");
+    if (f == nullptr) return set_error(WD_ERR_INVALID_ARG, "cannot open %s", path);
+    std::map<Key, MarchTuning> add;
+    char line[512];
+    int lineno = 0;
+    int rc = WD_OK;
+    while (rc == WD_OK && std::fgets(line, sizeof(line), f) != nullptr) {
+      ++lineno;
+      if (std::strchr(line, '\n') == nullptr && !std::feof(f)) {
+        rc = set_error(WD_ERR_INVALID_ARG, "%s:%d: line too long", path, lineno);
+        break;
+      }
+      if (lineno == 1) {
+        if (std::strncmp(line, kHeader, std::strlen(kHeader)) != 0)
+          rc = set_error(WD_ERR_INVALID_ARG, "%s: not a tuning file (header mismatch)", path);
+        continue;
+      }
+      int v[10];
+      char extra = 0;
+      const int got = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %c", &v[0], &v[1], &v[2], &v[3],
+                                  &v[4], &v[5], &v[6], &v[7], &v[8], &v[9], &extra);
+      if (got != 10) {
+        rc = set_error(WD_ERR_INVALID_ARG, "%s:%d: expected 10 integers", path, lineno);
+        break;
+      }
+      const int32_t dims[4] = {v[0], v[1], v[2], v[3]};
+      long V = 0;
+      const MarchTuning t{v[7], v[8], v[9]};
+      if (check_dims(dims, &V) != WD_OK || (v[4] != WD_FP64 && v[4] != WD_FP32 && v[4] != WD_FP16) ||
+          (v[5] != 0 && v[5] != 1) || v[6] < 1 || v[6] > kMaxMultiRhs ||
+          !march_tuning_valid(dims, v[4], v[6], t)) {
+        rc = set_error(WD_ERR_INVALID_ARG, "%s:%d: not a valid launch choice for its lattice", path,
+                       lineno);
+        break;
+      }
+      add[key_of(dims, v[4], v[5], v[6])] = t;
+    }
+    if (rc == WD_OK && lineno == 0) rc = set_error(WD_ERR_INVALID_ARG, "%s is empty", path);
+    std::fclose(f);
+    if (rc != WD_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const auto& [k, t] : add) g_cache[k] = t;
+    if (!g_cache.empty()) g_any.store(true, std::memory_order_release);
+    return WD_OK;
+  } catch (...) {
+    return set_error(WD_ERR_INTERNAL, "unexpected exception in wd_tune_load");
+  }
+}
+
+}  // extern "C"

@@ -81,4 +81,23 @@ hipError_t launch_dslash(const wd_gauge* g, double mass, const void* in, void* o
 hipError_t launch_dslash_multi(const wd_gauge* g, const double* masses, int nrhs, const int* fields,
                                const void* in, void* out, int flags, hipStream_t s);
 
+// Launch choices of the t-marching kernel that leave every site's arithmetic,
+// and so every result bit, unchanged: t steps per workgroup, right-hand sides
+// per workgroup, and the run length of tiles per XCD (0: hardware order).
+struct MarchTuning {
+  int32_t tb, gw, group;
+};
+// The default choice for a lattice, precision and nrhs; false when the
+// t-marching kernel does not apply (the one-site-per-lane kernel runs).
+bool march_default(const int32_t dims[4], int prec, int nrhs, MarchTuning* t);
+// Alternatives to the default (the default included), all valid.
+void march_candidates(const int32_t dims[4], int prec, int nrhs, MarchTuning* out, int* n, int cap);
+// Whether t may be used for a launch (bounds, lanes and LDS).
+bool march_tuning_valid(const int32_t dims[4], int prec, int nrhs, const MarchTuning& t);
+// launch_dslash_multi with an explicit choice (validated by the caller).
+hipError_t launch_dslash_tuned(const wd_gauge* g, const double* masses, int nrhs, const void* in,
+                               void* out, int flags, const MarchTuning& t, hipStream_t s);
+// The autotuner's choice registered for (dims, prec, c12, nrhs), if any.
+bool tuned_lookup(const int32_t dims[4], int prec, int c12, int nrhs, MarchTuning* t);
+
 }  // namespace wd

@@ -58,6 +58,15 @@ class wd_cg_stats(ctypes.Structure):
                 "reliable_updates": self.reliable_updates,
                 "true_rel_residual": self.true_rel_residual, "seconds": self.seconds}
 
+class wd_tune_result(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("eligible", ctypes.c_int32), ("tb", ctypes.c_int32),
+                ("gw", ctypes.c_int32), ("group", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("default_us", ctypes.c_double), ("best_us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class wd_server_cfg(ctypes.Structure):
     _fields_ = [("arena_dev", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
                 ("inner", ctypes.c_int32), ("check_every", ctypes.c_int32), ("delta", ctypes.c_double),
@@ -114,6 +123,12 @@ SIGNATURES = {
     "cg_solve_normal": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp,
                                        ctypes.POINTER(wd_cg_params), ctypes.POINTER(wd_cg_stats),
                                        _vp, ctypes.c_size_t, _vp]),
+    "wd_tune_dslash": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp,
+                                      ctypes.POINTER(wd_tune_result)]),
+    "wd_tune_lookup": (ctypes.c_int, [_dims_t, _i32, _i32, _i32, ctypes.POINTER(ctypes.c_int32)]),
+    "wd_tune_reset": (ctypes.c_int, []),
+    "wd_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "wd_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
 }
 
 
@@ -349,3 +364,31 @@ def wd_server_info(server) -> dict:
 
 def wd_server_destroy(server) -> int:
     return _check("wd_server_destroy", _L().wd_server_destroy(server))
+
+
+def wd_tune_dslash(g, nrhs, inp, out, ref, reps=10, stream=None) -> dict:
+    """Tunes the dslash launch for g's lattice and nrhs; returns the result fields."""
+    res = wd_tune_result()
+    _check("wd_tune_dslash", _L().wd_tune_dslash(_h(g), nrhs, _ptr(inp), _ptr(out), _ptr(ref), reps,
+                                                 _stream(stream), ctypes.byref(res)))
+    return res.as_dict()
+
+
+def wd_tune_lookup(dims, prec, compress12, nrhs):
+    """(tb, gw, group) registered for the key, or None."""
+    choice = (ctypes.c_int32 * 3)()
+    rc = _check("wd_tune_lookup", _L().wd_tune_lookup(_dims(dims), prec, int(bool(compress12)), nrhs,
+                                                      choice))
+    return tuple(choice) if rc == 1 else None
+
+
+def wd_tune_reset() -> int:
+    return _check("wd_tune_reset", _L().wd_tune_reset())
+
+
+def wd_tune_save(path) -> int:
+    return _check("wd_tune_save", _L().wd_tune_save(os.fsencode(path)))
+
+
+def wd_tune_load(path) -> int:
+    return _check("wd_tune_load", _L().wd_tune_load(os.fsencode(path)))
