@@ -76,6 +76,8 @@ def parse(argv=None):
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-RHS measurement")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG solves/s measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch choices (skip the autotuner)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain device copy of known size (PMC calibration)")
     return ap.parse_args(argv)
@@ -97,6 +99,20 @@ def copy_calibration(torch, nbytes=1 << 30, reps=5):
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) / 1e3 / reps
     return 2 * nbytes / t / 1e9
+
+
+TUNE = True  # set from --no-tune
+
+
+def tune(torch, w, g, nrhs, src):
+    """Runs the library's autotuner for g's lattice and nrhs (outside any timed
+    region); later launches of that key use its choice."""
+    if not TUNE:
+        return None
+    out, ref = g.spinor(nrhs), g.spinor(nrhs)
+    res = w.wd_tune_dslash(g.handle, nrhs, src, out, ref, reps=5)
+    del out, ref
+    return {k: (round(v, 2) if isinstance(v, float) else v) for k, v in res.items()}
 
 
 def time_applies(torch, w, g, src, dst, mass, steps, warmup):
@@ -138,16 +154,20 @@ def bench_multi(torch, w, li, DeviceGauge, prec="fp32", steps=50, warmup=5, inpu
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
+    tuned = tune(torch, w, g, nrhs, src)
     fused = timed(lambda: w.dslash_apply_multi(g.handle, masses, nrhs, src, dst, g.prec))
     one = g.spinor(1)
     res = g.spinor(1)
+    w.wd_spinor_import(g.handle, torch.from_numpy(psis[0]).cuda(), g.prec, 1, one)
+    tune(torch, w, g, 1, one)
     single = timed(lambda: w.dslash_apply(g.handle, 0.1, one, res, g.prec)) * nrhs
     comp = REAL_BYTES[prec] * 4 * 18 + nrhs * 2 * SPINOR_BYTES[prec]  # links once + 12 x (in + out)
     return {"workload": "wilson_dslash_multi_24x24x24x48_x12", "prec": prec, "links": "full",
             "gauge": "near-unity eps=0.3", "ms_per_apply": round(fused, 4),
             "gflops": round(nrhs * FLOPS_PER_SITE * V / (fused / 1e3) / 1e9, 1),
             "pct_hbm_peak": round(100 * comp * V / (fused / 1e3) / 1e9 / HBM_PEAK_GBS, 2),
-            "ms_12_single_applies": round(single, 4), "speedup_vs_single": round(single / fused, 3)}
+            "ms_12_single_applies": round(single, 4), "speedup_vs_single": round(single / fused, 3),
+            "tuning": tuned}
 
 
 def bench_cg(torch, w, li, DeviceGauge, reps=3):
@@ -164,10 +184,12 @@ def bench_cg(torch, w, li, DeviceGauge, reps=3):
         ghi = DeviceGauge(U, w.WD_FP64)
         glo = {w.WD_FP64: ghi, w.WD_FP32: DeviceGauge(U, w.WD_FP32),
                w.WD_FP16: DeviceGauge(U, w.WD_FP16)}
-        return ghi, glo, ghi.pack(b), ghi.spinor(1)
+        return ghi, glo, ghi.pack(b), ghi.spinor(1), b
 
     def run(dims, lat, inner, use_graph):
-        ghi, glo, bd, x = lat
+        ghi, glo, bd, x, b = lat
+        for g in {id(ghi): ghi, id(glo[inner]): glo[inner]}.values():
+            tune(torch, w, g, 1, g.pack(b))
         ws = torch.empty(w.cg_workspace_bytes(dims, 1, inner), dtype=torch.uint8, device="cuda")
         params = dict(tol=1e-10, max_iter=20000, inner=inner, delta=0.1, check_every=8, x0_given=0,
                       use_graph=use_graph)
@@ -306,6 +328,8 @@ def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=24, load=0.8, see
 
 def main(argv=None):
     args = parse(argv)
+    global TUNE
+    TUNE = not args.no_tune
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path is a single-GPU whole-lattice operator)", file=sys.stderr)
@@ -349,11 +373,12 @@ def main(argv=None):
         e1.record()
         torch.cuda.synchronize()
         pack_ms = e0.elapsed_time(e1)
+        tuned = tune(torch, w, g, 1, src)
         ms = time_applies(torch, w, g, src, dst, mass, steps, warmup)
-        return g, src, dst, ms, pack_ms
+        return g, src, dst, ms, pack_ms, tuned
 
     print(f"[bench] timing {args.prec} c12={args.c12}", file=sys.stderr, flush=True)
-    g, src, dst, ms, pack_ms = measure(args.prec, args.c12, args.steps, args.warmup)
+    g, src, dst, ms, pack_ms, tuned = measure(args.prec, args.c12, args.steps, args.warmup)
     t_s = ms / 1e3
     gflops = FLOPS_PER_SITE * V / t_s / 1e9
     cbytes = compulsory_bytes(args.prec, args.c12)
@@ -375,9 +400,9 @@ def main(argv=None):
                      ("fp16", False), ("fp16", True)):
             if (p, c) == (args.prec, args.c12):
                 continue
-            gv, sv, dv, msv, _ = measure(p, c, max(20, args.steps // 4), 5)
+            gv, sv, dv, msv, _, tv = measure(p, c, max(20, args.steps // 4), 5)
             variants[f"{p}{'_c12' if c else ''}"] = {
-                "ms_per_apply": round(msv, 5),
+                "ms_per_apply": round(msv, 5), "tuning": tv,
                 "gflops": round(FLOPS_PER_SITE * V / (msv / 1e3) / 1e9, 1),
                 "pct_hbm_peak": round(100 * compulsory_bytes(p, c) * V / (msv / 1e3) / 1e9
                                       / HBM_PEAK_GBS, 2)}
@@ -443,6 +468,7 @@ def main(argv=None):
                      "algorithmic_bytes_per_launch": cbytes * V},
         "parity": {"rel_err": parity, "tol": tol, "sites": int(len(sites)), "ok": parity <= tol},
         "pack_ms": round(pack_ms, 4),
+        "tuning": tuned,
         "torch_copy_gbs": round(copy_gbs, 1),
         "variants": variants,
         "multi_rhs": multi,
