@@ -166,8 +166,9 @@ WD_API int dslash_apply_multi(const wd_gauge* g, const double* masses_host, int3
  * choices of the operator of eq. (1), Sec. II-A, on this device).
  *
  * Only choices that leave every site's arithmetic unchanged are searched: t
- * steps per workgroup, right-hand sides per workgroup and the run length of
- * tiles per XCD of the t-marching kernel. A candidate is eligible only if its
+ * steps per workgroup, lane groups per workgroup, the run length of tiles
+ * per XCD and right-hand sides per lane (1 or 2; with 2 a lane loads each
+ * link once for both) of the t-marching kernel. A candidate is eligible only if its
  * output is bit-identical to the default choice's; the fastest eligible one
  * is kept in a process-wide cache keyed by (dims, prec, compress12, nrhs) and
  * used by every later dslash_apply / dslash_apply_multi / CG launch of that
@@ -177,8 +178,8 @@ WD_API int dslash_apply_multi(const wd_gauge* g, const double* masses_host, int3
 typedef struct wd_tune_result {
   int32_t candidates;  /* launch choices timed (0: this lattice uses the one-site-per-lane kernel) */
   int32_t eligible;    /* of those, bit-identical to the default choice */
-  int32_t tb, gw, group;  /* the choice kept: t steps and right-hand sides per workgroup, XCD run */
-  int32_t reserved;
+  int32_t tb, gw, group;  /* the choice kept: t steps and lane groups per workgroup, XCD run */
+  int32_t rb;          /* ... and right-hand sides per lane */
   double default_us;   /* average time per launch of the default choice */
   double best_us;      /* ... and of the choice kept */
 } wd_tune_result;
@@ -192,10 +193,10 @@ typedef struct wd_tune_result {
 WD_API int wd_tune_dslash(const wd_gauge* g, int32_t nrhs, const void* in_dev, void* out_dev,
                           void* ref_dev, int32_t reps, hipStream_t stream, wd_tune_result* result);
 
-/* 1 and choice = {tb, gw, group} if a choice is registered for the key, 0 if
- * not, negative for invalid arguments. */
+/* 1 and choice = {tb, gw, group, rb} if a choice is registered for the key,
+ * 0 if not, negative for invalid arguments. */
 WD_API int wd_tune_lookup(const int32_t dims[4], int32_t prec, int32_t compress12, int32_t nrhs,
-                          int32_t choice[3]);
+                          int32_t choice[4]);
 
 /* Forgets every registered choice. */
 WD_API int wd_tune_reset(void);

@@ -127,52 +127,98 @@ struct MarchParams {
   int ytiles;  // Y / ny
   int group;   // XCD run length (workgroups), 0 = hardware order
   int nrhs;    // right-hand sides of the launch
-  int gw;      // right-hand sides per workgroup (divides nrhs)
+  int gw;      // lane groups per workgroup
+  int rb;      // right-hand sides per lane (gw * rb divides nrhs)
 };
+
+// One hop for the RB right-hand sides of a lane: the link (direction MU at
+// site ls) is loaded once and applied to each one's neighbour spinor at site
+// nb. Each right-hand side sees exactly the operations of a one-field hop.
+template <int MU, int S, bool C12, int RB, typename SV, typename LV, typename R>
+__device__ __forceinline__ void hop_rb(const SV* const (&in)[RB], const LV* __restrict__ links, long V,
+                                       int nb, int ls, cx<R> (&acc)[RB][12]) {
+  cx<R> u[9];
+  load_link<C12>(links, V, MU, ls, u);
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    cx<R> psi[12];
+    load_spinor(in[r], V, nb, psi);
+    cx<R> h[6], g[6];
+    project<MU, S>(psi, h);
+    su3_mul<(S > 0)>(u, h, g);
+    reconstruct_add<MU, S>(g, acc[r]);
+  }
+}
+
+// The same with the neighbour spinors read from the LDS slices (slot li).
+template <int MU, int S, bool C12, int RB, typename SL, typename LV, typename R>
+__device__ __forceinline__ void lds_hop_rb(SL* const (&slice)[RB], int n, int li,
+                                           const LV* __restrict__ links, long V, int ls,
+                                           cx<R> (&acc)[RB][12]) {
+  cx<R> u[9];
+  load_link<C12>(links, V, MU, ls, u);
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    cx<R> psi[12];
+    lds_load_spinor(slice[r], n, li, psi);
+    cx<R> h[6], g[6];
+    project<MU, S>(psi, h);
+    su3_mul<(S > 0)>(u, h, g);
+    reconstruct_add<MU, S>(g, acc[r]);
+  }
+}
 
 // Hops of time t that involve sites outside the tile: z forward and
 // backward, and the y hops of the tile's edge rows.
-template <bool C12, typename SV, typename LV, typename R>
-__device__ __forceinline__ void outer_hops(const SV* __restrict__ in, const LV* __restrict__ links,
+template <bool C12, int RB, typename SV, typename LV, typename R>
+__device__ __forceinline__ void outer_hops(const SV* const (&in)[RB], const LV* __restrict__ links,
                                            long V, int st, int dzp, int dzm, bool y_fwd_out, int dyp,
-                                           bool y_bwd_out, int dym, cx<R> (&acc)[12]) {
-  hop<2, -1, C12>(in, links, V, st + dzp, st, acc);
-  hop<2, +1, C12>(in, links, V, st + dzm, st + dzm, acc);
-  if (y_fwd_out) hop<1, -1, C12>(in, links, V, st + dyp, st, acc);
-  if (y_bwd_out) hop<1, +1, C12>(in, links, V, st + dym, st + dym, acc);
+                                           bool y_bwd_out, int dym, cx<R> (&acc)[RB][12]) {
+  hop_rb<2, -1, C12>(in, links, V, st + dzp, st, acc);
+  hop_rb<2, +1, C12>(in, links, V, st + dzm, st + dzm, acc);
+  if (y_fwd_out) hop_rb<1, -1, C12>(in, links, V, st + dyp, st, acc);
+  if (y_bwd_out) hop_rb<1, +1, C12>(in, links, V, st + dym, st + dym, acc);
 }
 
-// MAXT: launch bound; a workgroup holds p.gw right-hand sides of one tile,
-// one group of n = X * ny lanes (and its own two LDS slices) each. The LDS
-// slices hold spinors in the arithmetic precision (FP32 for FP16 storage).
-template <typename T, bool C12, int MAXT>
+// MAXT: launch bound. A workgroup holds p.gw groups of n = X * ny lanes of
+// one tile; each lane carries RB right-hand sides (links loaded once for
+// all), each with its own two LDS slices. The LDS slices hold spinors in the
+// arithmetic precision (FP32 for FP16 storage).
+template <typename T, bool C12, int MAXT, int RB>
 __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
     const typename Packed<T>::S* __restrict__ in, typename Packed<T>::S* __restrict__ out,
     const typename Packed<T>::L* __restrict__ links, Geo geo, Diag<typename Packed<T>::R> diags,
     long stride, int gamma5, MarchParams p) {
   using R = typename Packed<T>::R;
   using SV = typename Packed<R>::S;
+  using GS = typename Packed<T>::S;
   constexpr int kPlanes = sizeof(R) == 8 ? 12 : 6;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int n = geo.X * p.ny;  // sites per tile == lanes per right-hand side
+  const int n = geo.X * p.ny;  // sites per tile == lanes per lane group
   const int slot = static_cast<int>(threadIdx.x) / n;
-  SV* buf0 = reinterpret_cast<SV*>(smem) + slot * 2 * kPlanes * n;
-  SV* buf1 = buf0 + kPlanes * n;
+  // slice (buffer f, right-hand side r) of this lane group
+  SV* const base = reinterpret_cast<SV*>(smem) + slot * 2 * RB * kPlanes * n;
   const long V = geo.V;
 
   const int tid = static_cast<int>(threadIdx.x) - slot * n;
   const int xl = tid % geo.X;
   const int yl = tid / geo.X;
-  // The p.gw right-hand sides of a workgroup march in lock step (one barrier
-  // per step), so a link line fetched for one of them is an L1/L2 hit for
-  // the others. Further groups of the same tile are consecutive workgroups.
-  const int groups = p.nrhs / p.gw;
+  // The lane groups of a workgroup march in lock step (one barrier per
+  // step), so a link line fetched for one of them is an L1/L2 hit for the
+  // others. Further workgroups of the same tile are consecutive.
+  const int groups = p.nrhs / (p.gw * RB);
   const int bb = tile_of_block(p.group);
-  const int rhs = (bb % groups) * p.gw + slot;
+  const int rhs0 = ((bb % groups) * p.gw + slot) * RB;
   const int b = bb / groups;
-  in += diags.idx[rhs] * stride;
-  out += diags.idx[rhs] * stride;
-  const R diag = diags.d[rhs];
+  const GS* inr[RB];
+  GS* outr[RB];
+  R diag[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    inr[r] = in + diags.idx[rhs0 + r] * stride;
+    outr[r] = out + diags.idx[rhs0 + r] * stride;
+    diag[r] = diags.d[rhs0 + r];
+  }
   const int yt = b % p.ytiles;
   const int z = (b / p.ytiles) % geo.Z;
   const int tblk = b / (p.ytiles * geo.Z);
@@ -196,26 +242,37 @@ __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
   const int dzp = z + 1 == geo.Z ? -(geo.Z - 1) * geo.XY : geo.XY;
   const int dzm = z == 0 ? (geo.Z - 1) * geo.XY : -geo.XY;
 
-  cx<R> acc[12];
+  cx<R> acc[RB][12];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[r][c] = {R(0), R(0)};
 
   // prologue: the carried hops of t0 (in the loop's order: outer hops, then
   // the backward t hop, so every site rounds alike) and the first slice in LDS
   {
     const int tm = t0 == 0 ? geo.T - 1 : t0 - 1;
     const int st = s0 + t0 * geo.XYZ;
-    outer_hops<C12>(in, links, V, st, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, acc);
-    hop<3, +1, C12>(in, links, V, s0 + tm * geo.XYZ, s0 + tm * geo.XYZ, acc);
-    cx<R> psi[12];
-    load_spinor(in, V, st, psi);
-    lds_store_spinor(buf0, n, tid, psi);
+    outer_hops<C12>(inr, links, V, st, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, acc);
+    hop_rb<3, +1, C12>(inr, links, V, s0 + tm * geo.XYZ, s0 + tm * geo.XYZ, acc);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      cx<R> psi[12];
+      load_spinor(inr[r], V, st, psi);
+      lds_store_spinor(base + (2 * r) * kPlanes * n, n, tid, psi);
+    }
   }
   __syncthreads();
 
   for (int t = t0; t < t1; ++t) {
-    SV* cur = ((t - t0) & 1) ? buf1 : buf0;
-    SV* nxt = ((t - t0) & 1) ? buf0 : buf1;
+    const int f = (t - t0) & 1;  // the buffer holding slice t
+    SV* cur[RB];
+    SV* nxt[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      cur[r] = base + (2 * r + f) * kPlanes * n;
+      nxt[r] = base + (2 * r + (f ^ 1)) * kPlanes * n;
+    }
     const int st = s0 + t * geo.XYZ;
     const int sn = t + 1 == geo.T ? s0 : st + geo.XYZ;  // the site at t+1
     const bool more = t + 1 < t1;
@@ -225,53 +282,48 @@ __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
     // whose spinors other workgroups are loading as their own slice now.
     cx<R> ut[9];
     load_link<C12>(links, V, 3, st, ut);
-    cx<R> nacc[12];
+    cx<R> nacc[RB][12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) nacc[c] = {R(0), R(0)};
-    {
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) nacc[r][c] = {R(0), R(0)};
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
       cx<R> psi[12];
-      load_spinor(in, V, sn, psi);
+      load_spinor(inr[r], V, sn, psi);
       if (more) {
-        lds_store_spinor(nxt, n, tid, psi);
-        outer_hops<C12>(in, links, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, nacc);
+        lds_store_spinor(nxt[r], n, tid, psi);
+        if (r == 0) outer_hops<C12>(inr, links, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, nacc);
       }
       cx<R> h[6], g[6];
       project<3, -1>(psi, h);
       su3_mul<false>(ut, h, g);
-      reconstruct_add<3, -1>(g, acc);
+      reconstruct_add<3, -1>(g, acc[r]);
     }
     // x hops and in-tile y hops from LDS
-    {
-      cx<R> psi[12];
-      lds_load_spinor(cur, n, lxp, psi);
-      hop_psi<0, -1, C12>(psi, links, V, st, acc);
-      lds_load_spinor(cur, n, lxm, psi);
-      hop_psi<0, +1, C12>(psi, links, V, st + dxm, acc);
-      if (!y_fwd_out) {
-        lds_load_spinor(cur, n, lyp, psi);
-        hop_psi<1, -1, C12>(psi, links, V, st, acc);
-      }
-      if (!y_bwd_out) {
-        lds_load_spinor(cur, n, lym, psi);
-        hop_psi<1, +1, C12>(psi, links, V, st + dym, acc);
-      }
-    }
+    lds_hop_rb<0, -1, C12>(cur, n, lxp, links, V, st, acc);
+    lds_hop_rb<0, +1, C12>(cur, n, lxm, links, V, st + dxm, acc);
+    if (!y_fwd_out) lds_hop_rb<1, -1, C12>(cur, n, lyp, links, V, st, acc);
+    if (!y_bwd_out) lds_hop_rb<1, +1, C12>(cur, n, lym, links, V, st + dym, acc);
     // epilogue of t; the backward t hop of t+1 joins the next accumulator
-    {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
       cx<R> psi[12];
-      lds_load_spinor(cur, n, tid, psi);
+      lds_load_spinor(cur[r], n, tid, psi);
       cx<R> o[12];
-      epilogue(psi, acc, diag, gamma5, o);
-      store_spinor(out, V, st, o);
+      epilogue(psi, acc[r], diag[r], gamma5, o);
+      store_spinor(outr[r], V, st, o);
       if (more) {
         cx<R> h[6], g[6];
         project<3, +1>(psi, h);
         su3_mul<true>(ut, h, g);
-        reconstruct_add<3, +1>(g, nacc);
+        reconstruct_add<3, +1>(g, nacc[r]);
       }
     }
 #pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = nacc[c];
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[r][c] = nacc[r][c];
     __syncthreads();
   }
 }
@@ -294,7 +346,7 @@ size_t march_lds_bytes(int threads, size_t real_bytes) {
 
 
 MarchParams march_params(const Geo& geo, size_t real_bytes, int nrhs) {
-  MarchParams p{0, 0, 0, 0, nrhs, 1};
+  MarchParams p{0, 0, 0, 0, nrhs, 1, 1};
   if (geo.X > kMarchMaxThreads) return p;
   int ny = 0;
   for (int d = 1; d <= geo.Y; ++d)
@@ -339,7 +391,7 @@ MarchParams march_params(const Geo& geo, size_t real_bytes, int nrhs) {
   return p;
 }
 
-template <typename T, bool C12, int MAXT>
+template <typename T, bool C12, int MAXT, int RB>
 hipError_t launch_march_t(const void* in, void* out, const void* links, const Geo& geo,
                           const Diag<typename Packed<T>::R>& diag, long stride, int g5,
                           const MarchParams& p, hipStream_t st) {
@@ -347,19 +399,19 @@ hipError_t launch_march_t(const void* in, void* out, const void* links, const Ge
   using LV = typename Packed<T>::L;
   using R = typename Packed<T>::R;
   const int n = geo.X * p.ny;
-  const size_t lds = p.gw * march_lds_bytes(n, sizeof(R));
+  const size_t lds = static_cast<size_t>(p.gw) * RB * march_lds_bytes(n, sizeof(R));
   // raise the kernel's dynamic LDS limit once to the whole LDS of a CU
   static std::atomic<int> attr_set{0};
   if (!attr_set.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&dslash_march_kernel<T, C12, MAXT>),
+        reinterpret_cast<const void*>(&dslash_march_kernel<T, C12, MAXT, RB>),
         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
     if (e != hipSuccess) return e;
     attr_set.store(1, std::memory_order_release);
   }
-  const unsigned nb = static_cast<unsigned>((p.nrhs / p.gw) * p.ytiles * geo.Z *
+  const unsigned nb = static_cast<unsigned>((p.nrhs / (p.gw * RB)) * p.ytiles * geo.Z *
                                             ((geo.T + p.tb - 1) / p.tb));
-  dslash_march_kernel<T, C12, MAXT><<<nb, p.gw * n, lds, st>>>(
+  dslash_march_kernel<T, C12, MAXT, RB><<<nb, p.gw * n, lds, st>>>(
       static_cast<const SV*>(in), static_cast<SV*>(out), static_cast<const LV*>(links), geo, diag,
       stride, g5, p);
   return hipGetLastError();
@@ -370,11 +422,14 @@ hipError_t launch_march(const void* in, void* out, const void* links, const Geo&
                         const Diag<typename Packed<T>::R>& diag, long stride, int g5,
                         const MarchParams& p, hipStream_t st) {
   if constexpr (sizeof(typename Packed<T>::R) == 4) {
+    if (p.rb == 2)  // two right-hand sides per lane: one lane group per workgroup
+      return launch_march_t<T, C12, kMarchMaxThreads, 2>(in, out, links, geo, diag, stride, g5, p,
+                                                         st);
     if (p.gw > 1)
-      return launch_march_t<T, C12, kMarchMultiThreads>(in, out, links, geo, diag, stride, g5, p,
-                                                        st);
+      return launch_march_t<T, C12, kMarchMultiThreads, 1>(in, out, links, geo, diag, stride, g5, p,
+                                                           st);
   }
-  return launch_march_t<T, C12, kMarchMaxThreads>(in, out, links, geo, diag, stride, g5, p, st);
+  return launch_march_t<T, C12, kMarchMaxThreads, 1>(in, out, links, geo, diag, stride, g5, p, st);
 }
 
 template <typename T, bool C12>
@@ -396,6 +451,7 @@ MarchParams with_tuning(MarchParams p, const MarchTuning& t) {
   p.tb = t.tb;
   p.gw = t.gw;
   p.group = t.group;
+  p.rb = t.rb;
   return p;
 }
 
@@ -465,7 +521,7 @@ bool march_default(const int32_t dims[4], int prec, int nrhs, MarchTuning* t) {
   if (WD_DSLASH_KERNEL != 0) return false;
   const MarchParams p = march_params(make_geo(dims), real_bytes_of(prec), nrhs);
   if (p.ny == 0) return false;
-  *t = MarchTuning{p.tb, p.gw, p.group};
+  *t = MarchTuning{p.tb, p.gw, p.group, p.rb};
   return true;
 }
 
@@ -475,13 +531,15 @@ bool march_tuning_valid(const int32_t dims[4], int prec, int nrhs, const MarchTu
   const MarchParams p = march_params(geo, real, nrhs);
   if (WD_DSLASH_KERNEL != 0 || p.ny == 0 || nrhs < 1 || nrhs > kMaxMultiRhs) return false;
   if (t.tb < 1 || t.tb > geo.T || t.group < 0) return false;
-  if (t.gw < 1 || nrhs % t.gw != 0) return false;
+  if (t.rb != 1 && t.rb != 2) return false;
+  if (t.gw < 1 || nrhs % (t.gw * t.rb) != 0) return false;
   const int n = geo.X * p.ny;
-  if (t.gw > 1) {  // several right-hand sides per workgroup: FP32 arithmetic only
+  if (t.gw > 1 || t.rb > 1) {  // several right-hand sides per workgroup: FP32 arithmetic only
     if (real != 4 || t.gw * n > kMarchMultiThreads) return false;
   }
-  if (static_cast<size_t>(t.gw) * march_lds_bytes(n, real) > kLdsBytes) return false;
-  const long nb = static_cast<long>(nrhs / t.gw) * p.ytiles * geo.Z * ((geo.T + t.tb - 1) / t.tb);
+  if (t.rb > 1 && t.gw != 1) return false;  // two per lane: one lane group per workgroup
+  if (static_cast<size_t>(t.gw) * t.rb * march_lds_bytes(n, real) > kLdsBytes) return false;
+  const long nb = static_cast<long>(nrhs / (t.gw * t.rb)) * p.ytiles * geo.Z * ((geo.T + t.tb - 1) / t.tb);
   return nb >= 1 && nb <= 0x7fffffffL;
 }
 
@@ -500,19 +558,21 @@ void march_candidates(const int32_t dims[4], int prec, int nrhs, MarchTuning* ou
     if (tb < 2 && nt > 1) break;
     if (ntb == 0 || tbs[ntb - 1] != tb) tbs[ntb++] = tb;
   }
-  for (int gw = 1; gw <= nrhs; ++gw) {
-    if (nrhs % gw != 0) continue;
-    for (int i = 0; i < ntb; ++i) {
-      const long nb = static_cast<long>(nrhs / gw) * p.ytiles * geo.Z * ((geo.T + tbs[i] - 1) / tbs[i]);
-      const int groups[2] = {0, nb % kNumXcd == 0 ? static_cast<int>(nb / kNumXcd) : 0};
-      for (int j = 0; j < (groups[1] > 0 ? 2 : 1); ++j) {
-        const MarchTuning t{tbs[i], gw, groups[j]};
-        if (!march_tuning_valid(dims, prec, nrhs, t)) continue;
-        if (t.tb == d.tb && t.gw == d.gw && t.group == d.group) continue;
-        if (*n < cap) out[(*n)++] = t;
+  for (int rb = 1; rb <= 2; ++rb)
+    for (int gw = 1; gw <= nrhs; ++gw) {
+      if (nrhs % (gw * rb) != 0) continue;
+      for (int i = 0; i < ntb; ++i) {
+        const long nb =
+            static_cast<long>(nrhs / (gw * rb)) * p.ytiles * geo.Z * ((geo.T + tbs[i] - 1) / tbs[i]);
+        const int groups[2] = {0, nb % kNumXcd == 0 ? static_cast<int>(nb / kNumXcd) : 0};
+        for (int j = 0; j < (groups[1] > 0 ? 2 : 1); ++j) {
+          const MarchTuning t{tbs[i], gw, groups[j], rb};
+          if (!march_tuning_valid(dims, prec, nrhs, t)) continue;
+          if (t.tb == d.tb && t.gw == d.gw && t.group == d.group && t.rb == d.rb) continue;
+          if (*n < cap) out[(*n)++] = t;
+        }
       }
     }
-  }
 }
 
 }  // namespace wd

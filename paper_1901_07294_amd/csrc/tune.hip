@@ -1,7 +1,8 @@
 // Autotuner of the t-marching dslash launch.
 //
 // Only choices that leave every site's arithmetic unchanged are tuned (t steps
-// per workgroup, right-hand sides per workgroup, XCD run length of tiles), so
+// per workgroup, lane groups per workgroup, XCD run length of tiles,
+// right-hand sides per lane), so
 // a candidate is eligible only if its output is bit-identical to the default
 // choice's output on the same input. The fastest eligible choice is kept in a
 // process-wide cache keyed by lattice, precision, link format and number of
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(kCompareThreads) void count_diff_kernel(const uint4
   if (local > 0) atomicAdd(count, local);
 }
 
-const char* kHeader = "# wilson dslash launch tuning v1: X Y Z T prec c12 nrhs tb gw group";
+const char* kHeader = "# wilson dslash launch tuning v2: X Y Z T prec c12 nrhs tb gw group rb";
 
 // Device resources of one tuning run, released on every path.
 struct TuneScratch {
@@ -162,6 +163,7 @@ int wd_tune_dslash(const wd_gauge* g, int32_t nrhs, const void* in_dev, void* ou
     result->tb = cand[best].tb;
     result->gw = cand[best].gw;
     result->group = cand[best].group;
+    result->rb = cand[best].rb;
     result->default_us = us[0];
     result->best_us = us[best];
     return WD_OK;
@@ -171,7 +173,7 @@ int wd_tune_dslash(const wd_gauge* g, int32_t nrhs, const void* in_dev, void* ou
 }
 
 int wd_tune_lookup(const int32_t dims[4], int32_t prec, int32_t compress12, int32_t nrhs,
-                   int32_t choice[3]) {
+                   int32_t choice[4]) {
   clear_error();
   long V = 0;
   int rc = check_dims(dims, &V);
@@ -183,6 +185,7 @@ int wd_tune_lookup(const int32_t dims[4], int32_t prec, int32_t compress12, int3
   choice[0] = t.tb;
   choice[1] = t.gw;
   choice[2] = t.group;
+  choice[3] = t.rb;
   return 1;
 }
 
@@ -207,9 +210,9 @@ int wd_tune_save(const char* path) {
     if (f == nullptr) return set_error(WD_ERR_INVALID_ARG, "cannot open %s for writing", path);
     bool ok = std::fprintf(f, "%s\n", kHeader) > 0;
     for (const auto& [k, t] : snap)
-      ok = ok && std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k),
+      ok = ok && std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k),
                               std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k),
-                              std::get<6>(k), t.tb, t.gw, t.group) > 0;
+                              std::get<6>(k), t.tb, t.gw, t.group, t.rb) > 0;
     ok = (std::fclose(f) == 0) && ok;
     return ok ? WD_OK : set_error(WD_ERR_INVALID_ARG, "writing %s failed", path);
   } catch (...) {
@@ -238,17 +241,17 @@ int wd_tune_load(const char* path) {
           rc = set_error(WD_ERR_INVALID_ARG, "%s: not a tuning file (header mismatch)", path);
         continue;
       }
-      int v[10];
+      int v[11];
       char extra = 0;
-      const int got = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %c", &v[0], &v[1], &v[2], &v[3],
-                                  &v[4], &v[5], &v[6], &v[7], &v[8], &v[9], &extra);
-      if (got != 10) {
-        rc = set_error(WD_ERR_INVALID_ARG, "%s:%d: expected 10 integers", path, lineno);
+      const int got = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %c", &v[0], &v[1], &v[2],
+                                  &v[3], &v[4], &v[5], &v[6], &v[7], &v[8], &v[9], &v[10], &extra);
+      if (got != 11) {
+        rc = set_error(WD_ERR_INVALID_ARG, "%s:%d: expected 11 integers", path, lineno);
         break;
       }
       const int32_t dims[4] = {v[0], v[1], v[2], v[3]};
       long V = 0;
-      const MarchTuning t{v[7], v[8], v[9]};
+      const MarchTuning t{v[7], v[8], v[9], v[10]};
       if (check_dims(dims, &V) != WD_OK || (v[4] != WD_FP64 && v[4] != WD_FP32 && v[4] != WD_FP16) ||
           (v[5] != 0 && v[5] != 1) || v[6] < 1 || v[6] > kMaxMultiRhs ||
           !march_tuning_valid(dims, v[4], v[6], t)) {

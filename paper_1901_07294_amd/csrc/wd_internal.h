@@ -82,10 +82,11 @@ hipError_t launch_dslash_multi(const wd_gauge* g, const double* masses, int nrhs
                                const void* in, void* out, int flags, hipStream_t s);
 
 // Launch choices of the t-marching kernel that leave every site's arithmetic,
-// and so every result bit, unchanged: t steps per workgroup, right-hand sides
-// per workgroup, and the run length of tiles per XCD (0: hardware order).
+// and so every result bit, unchanged: t steps per workgroup, lane groups per
+// workgroup, the run length of tiles per XCD (0: hardware order) and
+// right-hand sides per lane (1 or 2).
 struct MarchTuning {
-  int32_t tb, gw, group;
+  int32_t tb, gw, group, rb;
 };
 // The default choice for a lattice, precision and nrhs; false when the
 // t-marching kernel does not apply (the one-site-per-lane kernel runs).

@@ -60,11 +60,11 @@ class wd_cg_stats(ctypes.Structure):
 
 class wd_tune_result(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int32), ("eligible", ctypes.c_int32), ("tb", ctypes.c_int32),
-                ("gw", ctypes.c_int32), ("group", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("gw", ctypes.c_int32), ("group", ctypes.c_int32), ("rb", ctypes.c_int32),
                 ("default_us", ctypes.c_double), ("best_us", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class wd_server_cfg(ctypes.Structure):
@@ -375,8 +375,8 @@ def wd_tune_dslash(g, nrhs, inp, out, ref, reps=10, stream=None) -> dict:
 
 
 def wd_tune_lookup(dims, prec, compress12, nrhs):
-    """(tb, gw, group) registered for the key, or None."""
-    choice = (ctypes.c_int32 * 3)()
+    """(tb, gw, group, rb) registered for the key, or None."""
+    choice = (ctypes.c_int32 * 4)()
     rc = _check("wd_tune_lookup", _L().wd_tune_lookup(_dims(dims), prec, int(bool(compress12)), nrhs,
                                                       choice))
     return tuple(choice) if rc == 1 else None

@@ -45,7 +45,7 @@ def test_tuning_keeps_bits_and_registers_choice(prec, nrhs, c12):
     assert res["candidates"] >= 4
     assert res["eligible"] == res["candidates"]  # tuned knobs never change a bit
     assert 0 < res["best_us"] <= res["default_us"]
-    assert w.wd_tune_lookup(dims, g.prec, c12, nrhs) == (res["tb"], res["gw"], res["group"])
+    assert w.wd_tune_lookup(dims, g.prec, c12, nrhs) == (res["tb"], res["gw"], res["group"], res["rb"])
     after = g.spinor(nrhs)
     w.dslash_apply_multi(g.handle, masses, nrhs, src, after, g.prec)
     torch.cuda.synchronize()
@@ -72,3 +72,30 @@ def test_tuning_site_kernel_lattice_and_errors():
     with pytest.raises(w.WilsonError) as e:
         w.wd_tune_dslash(g.handle, 17, a, b, c)
     assert e.value.code == w.WD_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec,c12,nrhs,line", [
+    ("fp32", False, 4, "16 16 8 16 1 0 4 4 1 0 2"),   # two right-hand sides per lane, 2 lane pairs
+    ("fp16", True, 2, "16 16 8 16 2 1 2 16 1 8 2"),   # FP16 storage, 12-real links, XCD runs of 8
+])
+def test_loaded_choice_two_rhs_per_lane_keeps_bits(tmp_path, prec, c12, nrhs, line):
+    dims = (16, 16, 8, 16)
+    U = li.near_unity_gauge(dims, 51, 0.3)
+    psis = li.gaussian_spinors(dims, [52 + k for k in range(nrhs)])
+    masses = [0.05 + 0.1 * k for k in range(nrhs)]
+    g = DeviceGauge(U, PRECS[prec], c12)
+    src = g.pack(psis, nrhs=nrhs)
+    default = g.spinor(nrhs)
+    w.dslash_apply_multi(g.handle, masses, nrhs, src, default, g.prec, flags=w.WD_FLAG_GAMMA5)
+    f = tmp_path / "tune.txt"
+    f.write_text("# wilson dslash launch tuning v2: X Y Z T prec c12 nrhs tb gw group rb\n" + line + "\n")
+    w.wd_tune_load(str(f))
+    assert w.wd_tune_lookup(dims, g.prec, c12, nrhs)[3] == 2
+    tuned = g.spinor(nrhs)
+    w.dslash_apply_multi(g.handle, masses, nrhs, src, tuned, g.prec, flags=w.WD_FLAG_GAMMA5)
+    torch.cuda.synchronize()
+    assert torch.equal(default, tuned)
+    got = g.unpack(tuned, nrhs=nrhs)
+    for k in range(nrhs):
+        ref = oracle.gamma5_apply(oracle.dslash(U, psis[k], masses[k]))
+        assert rel(got[k], ref) <= TOL[PRECS[prec]]
