@@ -224,85 +224,69 @@ def bench_cg(torch, w, li, DeviceGauge, reps=3):
     return out
 
 
-def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=24, load=0.8, seed=5000):
-    """Request server under a Poisson stream of CG solves (tol 1e-10, FP32
-    inner iterations with FP64 reliable updates) on resident near-unity gauge
-    fields of four lattice sizes; 1..12 right-hand sides per request, masses
-    uniform in [0.05, 0.5]. Capacity is measured with a saturated queue, then
-    latencies at `load` times that rate."""
+def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=30, loads=(0.5, 0.8, 0.95), seed=5000):
+    """Request server under Poisson streams of CG solves (tol 1e-10, FP16-storage
+    inner iterations with FP64 reliable updates) on a resident pool of two
+    near-unity gauge fields per lattice size (8^4, 16^4, 24^3x48, 32^3x64);
+    1..12 right-hand sides per request, masses uniform in [0.05, 0.5].
+    Capacity is measured with a saturated queue, then latencies at each of
+    `loads` times that rate; a second server with a small arena forces
+    requests to queue."""
     import oracle
     from paper_1901_07294_amd.buffers import to_device
     sizes = [(8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 48), (32, 32, 32, 64)]
     nrhs_max = 12
-    arena = torch.empty(48 << 30, dtype=torch.uint8, device="cuda")
-    srv = w.wd_server_create(arena, w.WD_FP32, check_every=8, delta=0.1,
-                             max_rhs_per_group=nrhs_max, n_streams=4)
-    try:
+    rng = np.random.default_rng(seed)
+
+    def make_pool(srv, size_list, configs):
         lat = []
-        for i, d in enumerate(sizes):
-            U = li.near_unity_gauge(d, 5100 + i, 0.3)
-            Ud = to_device(U)
-            gid = w.wd_server_add_gauge(srv, d, Ud)
-            packer = DeviceGauge(Ud, w.WD_FP64)
-            del Ud
-            base = [li.gaussian_spinor(d, 5200 + 10 * i + k) for k in range(4)]
-            bs = np.stack([base[k % 4] for k in range(nrhs_max)])
-            pool = packer.pack(bs, nrhs=nrhs_max)   # shared, read-only right-hand sides
-            lat.append({"dims": d, "U": U if i < 2 else None, "gid": gid, "packer": packer,
-                        "pool": pool, "b": bs if i < 2 else None})
-        rng = np.random.default_rng(seed)
+        for i, d in enumerate(size_list):
+            for j in range(configs):
+                U = li.near_unity_gauge(d, 5100 + configs * i + j, 0.3)
+                Ud = to_device(U)
+                gid = w.wd_server_add_gauge(srv, d, Ud)
+                packer = DeviceGauge(Ud, w.WD_FP64)
+                del Ud
+                base = [li.gaussian_spinor(d, 5200 + 10 * i + k) for k in range(4)]
+                bs = np.stack([base[k % 4] for k in range(nrhs_max)])
+                pool = packer.pack(bs, nrhs=nrhs_max)   # shared, read-only right-hand sides
+                small = d[0] * d[1] * d[2] * d[3] <= 16 ** 4
+                lat.append({"dims": d, "U": U if small else None, "gid": gid, "packer": packer,
+                            "pool": pool, "b": bs if small else None})
+        return lat
 
-        def draw():
-            i = int(rng.integers(0, len(sizes)))
-            nrhs = int(rng.integers(1, nrhs_max + 1))
-            return i, list(rng.uniform(0.05, 0.5, nrhs))
+    def draw(lat, max_rhs):
+        i = int(rng.integers(0, len(lat)))
+        nrhs = int(rng.integers(1, max_rhs + 1))
+        return i, list(rng.uniform(0.05, 0.5, nrhs))
 
-        def submit(i, masses):
-            L = lat[i]
-            x = L["packer"].spinor(len(masses))
-            t = w.cg_submit(srv, L["gid"], masses, L["pool"], x, tol=1e-10)
-            return t, x
-
-        def drain(live, done, deadline):
-            while live:
-                assert time.time() < deadline, "serving measurement timed out"
-                for t in list(live):
-                    rc, res = w.cg_poll(srv, t)
-                    if rc != w.WD_PENDING:
-                        done[t] = (rc, res, live.pop(t))
-                time.sleep(0.0005)
-
-        # capacity: everything queued at once
-        t0 = time.time()
+    def run_stream(srv, lat, arrivals, max_rhs):
+        """Submits at the given times (s; None = all at once); returns {ticket: (rc, res, req)}."""
         live, done = {}, {}
-        for _ in range(n_closed):
-            i, m = draw()
-            t, x = submit(i, m)
-            live[t] = (i, m, x)
-        drain(live, done, t0 + 600)
-        makespan = time.time() - t0
-        capacity = n_closed / makespan
-        # open loop at `load` x capacity
-        lam = load * capacity
-        arrivals = np.cumsum(rng.exponential(1.0 / lam, n_open))
-        live, done = {}, {}
+
+        def poll():
+            for t in list(live):
+                rc, res = w.cg_poll(srv, t)
+                if rc != w.WD_PENDING:
+                    done[t] = (rc, res, live.pop(t))
+
         t0 = time.time()
         for a in arrivals:
-            while time.time() - t0 < a:
-                for t in list(live):
-                    rc, res = w.cg_poll(srv, t)
-                    if rc != w.WD_PENDING:
-                        done[t] = (rc, res, live.pop(t))
+            while a is not None and time.time() - t0 < a:
+                poll()
                 time.sleep(0.0005)
-            i, m = draw()
-            t, x = submit(i, m)
+            i, m = draw(lat, max_rhs)
+            x = lat[i]["packer"].spinor(len(m))
+            t = w.cg_submit(srv, lat[i]["gid"], m, lat[i]["pool"], x, tol=1e-10)
             live[t] = (i, m, x)
-        drain(live, done, time.time() + 600)
-        wall = time.time() - t0
-        lat_s = np.array([res["t_done"] - res["t_submit"] for rc, res, _ in done.values()])
-        nrhs_total = sum(len(v[2][1]) for v in done.values())
-        ok = sum(rc == w.WD_OK for rc, _, _ in done.values())
-        # oracle check of the small-lattice results
+        deadline = time.time() + 600
+        while live:
+            assert time.time() < deadline, "serving measurement timed out"
+            poll()
+            time.sleep(0.0005)
+        return done, time.time() - t0
+
+    def worst_residual(lat, done):
         worst = 0.0
         for rc, res, (i, m, x) in done.values():
             L = lat[i]
@@ -313,17 +297,66 @@ def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=24, load=0.8, see
             for k in range(len(m)):
                 r = L["b"][k] - oracle.normal_op(L["U"], m[k], xs[k])
                 worst = max(worst, float(np.linalg.norm(r) / np.linalg.norm(L["b"][k])))
-        info = w.wd_server_info(srv)
-        return {"workload": "cg_requests_8^4_16^4_24^3x48_32^3x64_poisson", "inner": "fp32+fp64_reliable",
-                "tol": 1e-10, "capacity_req_per_s": round(capacity, 3), "offered_load": load,
-                "requests": n_open, "ok": int(ok), "req_per_s": round(n_open / wall, 3),
-                "rhs_solves_per_s": round(nrhs_total / wall, 2),
-                "p50_ms": round(float(np.percentile(lat_s, 50)) * 1e3, 2),
-                "p99_ms": round(float(np.percentile(lat_s, 99)) * 1e3, 2),
-                "max_true_rel_residual_small_lattices": worst,
-                "arena_peak_gb": round(info["arena_peak"] / 1e9, 2)}
+        return worst
+
+    def pct(v, q):
+        return round(float(np.percentile(v, q)) * 1e3, 2)
+
+    out = {"workload": "cg_requests_8^4_16^4_24^3x48_32^3x64_poisson", "inner": "fp16+fp64_reliable",
+           "tol": 1e-10, "gauge_pool": "2 near-unity configs per size (seeds 5100..5107)"}
+    arena = torch.empty(48 << 30, dtype=torch.uint8, device="cuda")
+    srv = w.wd_server_create(arena, w.WD_FP16, check_every=8, delta=0.1,
+                             max_rhs_per_group=nrhs_max, n_streams=4)
+    try:
+        lat = make_pool(srv, sizes, 2)
+        done, makespan = run_stream(srv, lat, [None] * n_closed, nrhs_max)
+        capacity = n_closed / makespan
+        out["capacity_req_per_s"] = round(capacity, 3)
+        out["levels"] = []
+        worst = worst_residual(lat, done)
+        for load in loads:
+            lam = load * capacity
+            arrivals = list(np.cumsum(rng.exponential(1.0 / lam, n_open)))
+            done, wall = run_stream(srv, lat, arrivals, nrhs_max)
+            lat_s = np.array([res["t_done"] - res["t_submit"] for rc, res, _ in done.values()])
+            wait_s = np.array([res["t_start"] - res["t_submit"] for rc, res, _ in done.values()])
+            nrhs_total = sum(len(v[2][1]) for v in done.values())
+            out["levels"].append({
+                "offered_load": load, "requests": n_open,
+                "ok": int(sum(rc == w.WD_OK for rc, _, _ in done.values())),
+                "req_per_s": round(n_open / wall, 3), "rhs_solves_per_s": round(nrhs_total / wall, 2),
+                "p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99),
+                "queue_wait_p50_ms": pct(wait_s, 50), "queue_wait_p99_ms": pct(wait_s, 99)})
+            worst = max(worst, worst_residual(lat, done))
+        out["max_true_rel_residual_small_lattices"] = worst
+        out["arena_peak_gb"] = round(w.wd_server_info(srv)["arena_peak"] / 1e9, 2)
     finally:
         w.wd_server_destroy(srv)
+        del arena
+    # a small arena: the two smallest sizes, room for the gauge fields and one group
+    small_sizes = sizes[:2]
+    per_group = (2 * w.wd_spinor_bytes(small_sizes[1], w.WD_FP64, 4) +
+                 w.cg_workspace_bytes(small_sizes[1], 4, w.WD_FP16))
+    gauges = sum(2 * (w.wd_gauge_bytes(d, w.WD_FP64, 0) + w.wd_gauge_bytes(d, w.WD_FP16, 0) + 512)
+                 for d in small_sizes)
+    arena_bytes = gauges + per_group + (1 << 20)
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    srv = w.wd_server_create(arena, w.WD_FP16, check_every=8, delta=0.1, max_rhs_per_group=4,
+                             n_streams=2)
+    try:
+        lat = make_pool(srv, small_sizes, 2)
+        done, wall = run_stream(srv, lat, [None] * 16, 4)
+        wait_s = np.array([res["t_start"] - res["t_submit"] for rc, res, _ in done.values()])
+        info = w.wd_server_info(srv)
+        out["small_arena"] = {
+            "arena_mb": round(arena_bytes / 1e6, 1), "requests": 16,
+            "ok": int(sum(rc == w.WD_OK for rc, _, _ in done.values())),
+            "arena_peak_mb": round(info["arena_peak"] / 1e6, 1),
+            "queue_wait_p50_ms": pct(wait_s, 50), "queue_wait_max_ms": pct(wait_s, 100),
+            "max_true_rel_residual": worst_residual(lat, done)}
+    finally:
+        w.wd_server_destroy(srv)
+    return out
 
 
 def main(argv=None):
