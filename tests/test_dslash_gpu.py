@@ -30,6 +30,9 @@ SHAPES = [
     (32, 32, 16, 11),  # t-marching, 3 steps per workgroup, ragged last t block
     (24, 24, 4, 8),    # t-marching, 24-wide rows (3 waves), 3 y tiles per plane
     (64, 2, 2, 3),     # t-marching, extent-2 y and z
+    (64, 1, 1, 1),     # t-marching, one site thick in y, z and t: every y/z/t hop lands on itself
+    (128, 1, 2, 2),    # t-marching, two-step march with extent-1 y
+    (96, 2, 1, 5),     # t-marching, extent-1 z, odd T
 ]
 
 

@@ -101,6 +101,7 @@ SHAPES = [
     (12, 10, 6, 14),   # many tiles + ragged tail
     (32, 32, 16, 11),  # t-marching, ragged last t block
     (24, 24, 4, 8),    # t-marching, 3 y tiles per plane
+    (64, 1, 1, 1),     # t-marching, extent 1 in y, z and t
 ]
 
 

@@ -21,7 +21,7 @@ def _device():
     torch.cuda.set_device(0)
 
 
-SHAPES = [(4, 4, 4, 4), (5, 3, 7, 4), (32, 32, 16, 11), (24, 24, 4, 8), (16, 8, 8, 8)]
+SHAPES = [(4, 4, 4, 4), (5, 3, 7, 4), (32, 32, 16, 11), (24, 24, 4, 8), (16, 8, 8, 8), (64, 1, 2, 1)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
