@@ -3,7 +3,7 @@
 //
 // A packed FP64 or FP32 field (fields.h) is a flat array of 16-byte
 // elements: 12 per site in FP64 (double2), 6 per site in FP32 (float4), in
-// blocks of 64 sites. Their elementwise kernels walk that flat array; the
+// blocks of kLayoutBlock sites. Their elementwise kernels walk that flat array; the
 // reductions skip the padding sites of the last block. An FP16 field shares
 // one scale among the 24 reals of a site, so its kernels work site by site
 // (one thread per site, real sites only), in FP32 arithmetic, and store
@@ -47,7 +47,7 @@ __device__ __forceinline__ double norm2(float4 a) {
 // Is flat element e of a packed field of P elements per site a real site?
 template <int P>
 __device__ __forceinline__ bool real_site(long e, long V) {
-  return (e / (P * 64)) * 64 + (e % 64) < V;
+  return (e / (P * kLayoutBlock)) * kLayoutBlock + (e % kLayoutBlock) < V;
 }
 
 template <typename T>
@@ -106,18 +106,18 @@ __global__ __launch_bounds__(kThreads) void update_xr_kernel(double2* __restrict
       re.y = fmar(-alpha, ae.y, re.y);
     } else {
       // FP32 element j of a block holds FP64 elements 2j and 2j+1 of the same sites
-      const long blk = e / (6 * 64);
-      const long j = (e / 64) % 6;
-      const long lane = e % 64;
-      const long h0 = (blk * 12 + 2 * j) * 64 + lane;
+      const long blk = e / (6 * kLayoutBlock);
+      const long j = (e / kLayoutBlock) % 6;
+      const long lane = e % kLayoutBlock;
+      const long h0 = (blk * 12 + 2 * j) * kLayoutBlock + lane;
       double2 x0 = xk[h0];
-      double2 x1 = xk[h0 + 64];
+      double2 x1 = xk[h0 + kLayoutBlock];
       x0.x = fmar(alpha, static_cast<double>(pe.x), x0.x);
       x0.y = fmar(alpha, static_cast<double>(pe.y), x0.y);
       x1.x = fmar(alpha, static_cast<double>(pe.z), x1.x);
       x1.y = fmar(alpha, static_cast<double>(pe.w), x1.y);
       xk[h0] = x0;
-      xk[h0 + 64] = x1;
+      xk[h0 + kLayoutBlock] = x1;
       const float a = static_cast<float>(alpha);
       re.x = fmar(-a, ae.x, re.x);
       re.y = fmar(-a, ae.y, re.y);
@@ -189,12 +189,12 @@ __global__ __launch_bounds__(kThreads) void demote_kernel(float4* __restrict__ l
   const double2* hk = hi + k * nhi;
   for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
        e += static_cast<long>(gridDim.x) * kThreads) {
-    const long blk = e / (6 * 64);
-    const long j = (e / 64) % 6;
-    const long lane = e % 64;
-    const long h0 = (blk * 12 + 2 * j) * 64 + lane;
+    const long blk = e / (6 * kLayoutBlock);
+    const long j = (e / kLayoutBlock) % 6;
+    const long lane = e % kLayoutBlock;
+    const long h0 = (blk * 12 + 2 * j) * kLayoutBlock + lane;
     const double2 a = hk[h0];
-    const double2 c = hk[h0 + 64];
+    const double2 c = hk[h0 + kLayoutBlock];
     lk[e] = make_float4(static_cast<float>(a.x), static_cast<float>(a.y), static_cast<float>(c.x),
                         static_cast<float>(c.y));
   }

@@ -104,12 +104,13 @@ __global__ __launch_bounds__(kBlock) void pack_gauge_kernel(const double2* __res
     for (int j = 0; j < 3; ++j) {
       const double2 a = src[2 * j];
       const double2 b = src[2 * j + 1];
-      d[pidx(s, mu * 3 + j, 12, V)] = h4{to_half(a.x), to_half(a.y), to_half(b.x), to_half(b.y)};
+      d[pidx<kHalfBlock>(s, mu * 3 + j, 12, V)] = h4{to_half(a.x), to_half(a.y), to_half(b.x), to_half(b.y)};
     }
   } else {
     h2* d = static_cast<h2*>(dst);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) d[pidx(s, mu * 9 + k, 36, V)] = h2{to_half(src[k].x), to_half(src[k].y)};
+    for (int k = 0; k < 9; ++k)
+      d[pidx<kHalfBlock>(s, mu * 9 + k, 36, V)] = h2{to_half(src[k].x), to_half(src[k].y)};
   }
 }
 

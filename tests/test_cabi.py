@@ -60,8 +60,10 @@ def test_version_and_sizes(lib):
     assert w.wd_spinor_bytes(d, w.WD_FP16, 12) == 12 * 52 * V
     assert w.wd_gauge_bytes(d, w.WD_FP16, 0) == 144 * V
     assert w.wd_gauge_bytes(d, w.WD_FP16, 1) == 96 * V
-    # padding to whole blocks of 64 sites
-    assert w.wd_spinor_bytes((5, 3, 7, 4), w.WD_FP16, 1) == 448 * 52
+    # padding to whole blocks of 2048 sites
+    assert w.wd_spinor_bytes((5, 3, 7, 4), w.WD_FP16, 1) == 2048 * 52
+    assert w.wd_spinor_bytes((16, 16, 16, 9), w.WD_FP64, 2) == 2 * 36864 * 192
+    assert w.wd_spinor_bytes((17, 16, 16, 9), w.WD_FP64, 1) == 40960 * 192
 
 
 def test_size_queries_reject_bad_arguments(lib):
