@@ -217,11 +217,11 @@ WD_API int wd_tune_load(const char* path);
  * applied to a quark field. D^dag D = Q^2 with the Hermitian Q = gamma5 D, so
  * every iteration applies dslash twice. With inner = WD_FP32 or WD_FP16 the
  * iterations run on fields of that precision (g_lo; FP16 storage keeps FP32
- * arithmetic) while the solution is accumulated in FP64 and the residual is
- * recomputed in FP64 (b - D^dag D x with g_hi) whenever the inner residual
- * has dropped by delta since the last recompute or claims convergence
- * ("reliable updates"); convergence is always decided on that FP64 true
- * residual.
+ * arithmetic) and accumulate the solution increments in FP32; whenever the
+ * inner residual has dropped by delta since the last recompute or claims
+ * convergence, the increments are added into the FP64 solution and the
+ * residual is recomputed in FP64 (b - D^dag D x with g_hi: "reliable
+ * updates"). Convergence is always decided on that FP64 true residual.
  * ------------------------------------------------------------------------ */
 
 typedef struct wd_cg_params {

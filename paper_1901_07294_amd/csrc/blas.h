@@ -37,8 +37,12 @@ enum : int { kFinPap = 0, kFinIterRr = 1, kFinTrueRr = 2, kFinNorm = 3 };
 // partial sums of a reduction depends only on the lattice and precision.
 hipError_t blas_norm2(const void* v, int prec, long n, long V, const RhsSet& set, double* partials,
                       double* scal, int mode, hipStream_t st);
-hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nhi,
+// x += alpha p, r -= alpha Ap: x is the FP64 solution for FP64 vectors, else
+// the FP32 accumulator x_lo (nlo32 16-byte FP32 elements per right-hand side).
+hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nlo32,
                           long V, const RhsSet& set, double* partials, double* scal, hipStream_t st);
+// x_hi += x_lo, then x_lo = 0
+hipError_t blas_flush_x(void* hi, void* lo, long nlo32, long nhi, const RhsSet& set, hipStream_t st);
 hipError_t blas_update_p(void* p, const void* r, int prec, long n, long V, const RhsSet& set,
                          const double* scal, hipStream_t st);
 hipError_t blas_residual(void* r, const void* b, long n, long V, const RhsSet& set, double* partials,

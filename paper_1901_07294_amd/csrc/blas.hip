@@ -77,17 +77,20 @@ __global__ __launch_bounds__(kThreads) void norm2_partial_kernel(const T* __rest
   if (threadIdx.x == 0) partials[set.idx[slot] * gridDim.x + blockIdx.x] = s;
 }
 
-// x_hi += alpha p ; r -= alpha Ap ; partial |r|^2   (alpha from the scalars)
+// x += alpha p ; r -= alpha Ap ; partial |r|^2   (alpha from the scalars).
+// FP64 vectors update the FP64 solution x_hi; FP32 vectors update the FP32
+// accumulator x_lo (same layout as p), which is added into x_hi at each
+// reliable update.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void update_xr_kernel(double2* __restrict__ x, T* __restrict__ r,
+__global__ __launch_bounds__(kThreads) void update_xr_kernel(T* __restrict__ x, T* __restrict__ r,
                                                              const T* __restrict__ p,
-                                                             const T* __restrict__ ap, long n, long nhi,
-                                                             long V, RhsSet set,
+                                                             const T* __restrict__ ap, long n, long V,
+                                                             RhsSet set,
                                                              const double* __restrict__ scal,
                                                              double* __restrict__ partials) {
   const int k = set.idx[blockIdx.y];
   const double alpha = scal[k * kScalars + kAlpha];
-  double2* xk = x + k * nhi;
+  T* xk = x + k * n;
   T* rk = r + k * n;
   const T* pk = p + k * n;
   const T* apk = ap + k * n;
@@ -97,38 +100,56 @@ __global__ __launch_bounds__(kThreads) void update_xr_kernel(double2* __restrict
     const T pe = pk[e];
     T re = rk[e];
     const T ae = apk[e];
+    T xe = xk[e];
     if constexpr (Elems<T>::P == 12) {
-      double2 xe = xk[e];
       xe.x = fmar(alpha, pe.x, xe.x);
       xe.y = fmar(alpha, pe.y, xe.y);
-      xk[e] = xe;
       re.x = fmar(-alpha, ae.x, re.x);
       re.y = fmar(-alpha, ae.y, re.y);
     } else {
-      // FP32 element j of a block holds FP64 elements 2j and 2j+1 of the same sites
-      const long blk = e / (6 * kLayoutBlock);
-      const long j = (e / kLayoutBlock) % 6;
-      const long lane = e % kLayoutBlock;
-      const long h0 = (blk * 12 + 2 * j) * kLayoutBlock + lane;
-      double2 x0 = xk[h0];
-      double2 x1 = xk[h0 + kLayoutBlock];
-      x0.x = fmar(alpha, static_cast<double>(pe.x), x0.x);
-      x0.y = fmar(alpha, static_cast<double>(pe.y), x0.y);
-      x1.x = fmar(alpha, static_cast<double>(pe.z), x1.x);
-      x1.y = fmar(alpha, static_cast<double>(pe.w), x1.y);
-      xk[h0] = x0;
-      xk[h0 + kLayoutBlock] = x1;
       const float a = static_cast<float>(alpha);
+      xe.x = fmar(a, pe.x, xe.x);
+      xe.y = fmar(a, pe.y, xe.y);
+      xe.z = fmar(a, pe.z, xe.z);
+      xe.w = fmar(a, pe.w, xe.w);
       re.x = fmar(-a, ae.x, re.x);
       re.y = fmar(-a, ae.y, re.y);
       re.z = fmar(-a, ae.z, re.z);
       re.w = fmar(-a, ae.w, re.w);
     }
+    xk[e] = xe;
     rk[e] = re;
     if (real_site<Elems<T>::P>(e, V)) s += norm2(re);
   }
   s = block_sum(s);
   if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
+}
+
+// x_hi += x_lo (FP32 element j of a block holds FP64 elements 2j and 2j+1 of
+// the same sites), then x_lo = 0
+__global__ __launch_bounds__(kThreads) void flush_x_kernel(double2* __restrict__ hi,
+                                                           float4* __restrict__ lo, long n, long nhi,
+                                                           RhsSet set) {
+  const int k = set.idx[blockIdx.y];
+  double2* hk = hi + k * nhi;
+  float4* lk = lo + k * n;
+  for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
+       e += static_cast<long>(gridDim.x) * kThreads) {
+    const long blk = e / (6 * kLayoutBlock);
+    const long j = (e / kLayoutBlock) % 6;
+    const long lane = e % kLayoutBlock;
+    const long h0 = (blk * 12 + 2 * j) * kLayoutBlock + lane;
+    const float4 l = lk[e];
+    double2 x0 = hk[h0];
+    double2 x1 = hk[h0 + kLayoutBlock];
+    x0.x += l.x;
+    x0.y += l.y;
+    x1.x += l.z;
+    x1.y += l.w;
+    hk[h0] = x0;
+    hk[h0 + kLayoutBlock] = x1;
+    lk[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
 }
 
 // p = r + beta p
@@ -269,15 +290,15 @@ __global__ __launch_bounds__(kThreads) void norm2_half_kernel(const h8* __restri
   if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
 }
 
-// x_hi += alpha p ; r -= alpha Ap (FP32, requantised) ; partial |r|^2
+// x_lo += alpha p (FP32 accumulator, FP32 layout) ; r -= alpha Ap (FP32,
+// requantised) ; partial |r|^2
 __global__ __launch_bounds__(kThreads) void update_xr_half_kernel(
-    double2* __restrict__ x, h8* __restrict__ r, const h8* __restrict__ p, const h8* __restrict__ ap,
-    long units, long nhi, long V, RhsSet set, const double* __restrict__ scal,
+    float4* __restrict__ x, h8* __restrict__ r, const h8* __restrict__ p, const h8* __restrict__ ap,
+    long units, long nlo32, long V, RhsSet set, const double* __restrict__ scal,
     double* __restrict__ partials) {
   const int k = set.idx[blockIdx.y];
-  const double alpha = scal[k * kScalars + kAlpha];
-  const float a = static_cast<float>(alpha);
-  double2* xk = x + k * nhi;
+  const float a = static_cast<float>(scal[k * kScalars + kAlpha]);
+  float4* xk = x + k * nlo32;
   h8* rk = r + k * units;
   double s = 0.0;
   WD_SITE_LOOP(i, V) {
@@ -286,13 +307,16 @@ __global__ __launch_bounds__(kThreads) void update_xr_half_kernel(
     load_spinor(rk, V, static_cast<int>(i), rv);
     load_spinor(ap + k * units, V, static_cast<int>(i), av);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      double2 xe = xk[pidx(i, c, 12, V)];
-      xe.x = fmar(alpha, static_cast<double>(pv[c].re), xe.x);
-      xe.y = fmar(alpha, static_cast<double>(pv[c].im), xe.y);
-      xk[pidx(i, c, 12, V)] = xe;
-      rv[c] = {fmar(-a, av[c].re, rv[c].re), fmar(-a, av[c].im, rv[c].im)};
+    for (int j = 0; j < 6; ++j) {
+      float4 xe = xk[pidx(i, j, 6, V)];
+      xe.x = fmar(a, pv[2 * j].re, xe.x);
+      xe.y = fmar(a, pv[2 * j].im, xe.y);
+      xe.z = fmar(a, pv[2 * j + 1].re, xe.z);
+      xe.w = fmar(a, pv[2 * j + 1].im, xe.w);
+      xk[pidx(i, j, 6, V)] = xe;
     }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rv[c] = {fmar(-a, av[c].re, rv[c].re), fmar(-a, av[c].im, rv[c].im)};
     s += store_half_site(rk, i, rv);
   }
   s = block_sum(s);
@@ -397,25 +421,30 @@ hipError_t blas_norm2(const void* v, int prec, long n, long V, const RhsSet& set
   return hipGetLastError();
 }
 
-hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nhi,
+hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nlo32,
                           long V, const RhsSet& set, double* partials, double* scal, hipStream_t st) {
   const dim3 g = grid(prec == WD_FP16 ? V : n, set.n);
-  auto* xh = static_cast<double2*>(x);
   if (prec == WD_FP64)
-    update_xr_kernel<double2><<<g, kThreads, 0, st>>>(xh, static_cast<double2*>(r),
+    update_xr_kernel<double2><<<g, kThreads, 0, st>>>(static_cast<double2*>(x), static_cast<double2*>(r),
                                                        static_cast<const double2*>(p),
-                                                       static_cast<const double2*>(ap), n, nhi, V,
-                                                       set, scal, partials);
+                                                       static_cast<const double2*>(ap), n, V, set,
+                                                       scal, partials);
   else if (prec == WD_FP32)
-    update_xr_kernel<float4><<<g, kThreads, 0, st>>>(xh, static_cast<float4*>(r),
+    update_xr_kernel<float4><<<g, kThreads, 0, st>>>(static_cast<float4*>(x), static_cast<float4*>(r),
                                                       static_cast<const float4*>(p),
-                                                      static_cast<const float4*>(ap), n, nhi, V,
-                                                      set, scal, partials);
+                                                      static_cast<const float4*>(ap), n, V, set, scal,
+                                                      partials);
   else
-    update_xr_half_kernel<<<g, kThreads, 0, st>>>(xh, static_cast<h8*>(r), static_cast<const h8*>(p),
-                                                  static_cast<const h8*>(ap), n, nhi, V, set, scal,
-                                                  partials);
+    update_xr_half_kernel<<<g, kThreads, 0, st>>>(static_cast<float4*>(x), static_cast<h8*>(r),
+                                                  static_cast<const h8*>(p), static_cast<const h8*>(ap),
+                                                  n, nlo32, V, set, scal, partials);
   finalize_kernel<<<set.n, kThreads, 0, st>>>(partials, static_cast<int>(g.x), set, kFinIterRr, scal);
+  return hipGetLastError();
+}
+
+hipError_t blas_flush_x(void* hi, void* lo, long nlo32, long nhi, const RhsSet& set, hipStream_t st) {
+  flush_x_kernel<<<grid(nlo32, set.n), kThreads, 0, st>>>(static_cast<double2*>(hi),
+                                                          static_cast<float4*>(lo), nlo32, nhi, set);
   return hipGetLastError();
 }
 

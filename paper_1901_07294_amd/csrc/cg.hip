@@ -7,10 +7,11 @@
 // A = D^dag D = Q^2 with the Hermitian Q = gamma5 D, so one CG iteration is two
 // dslash applications (gamma5 folded into their epilogue) and <p, A p> =
 // |Q p|^2. With lower-precision inner iterations (FP32, or FP16 storage with
-// FP32 arithmetic) the solution is accumulated in FP64, and whenever the
-// iterated residual has fallen by the factor delta since the last true
-// residual (or claims convergence), the residual is recomputed in FP64 as
-// b - A x ("reliable update") and the inner residual restarted from it.
+// FP32 arithmetic) the solution increments are accumulated in an FP32 vector,
+// and whenever the iterated residual has fallen by the factor delta since the
+// last true residual (or claims convergence), that vector is added into the
+// FP64 solution, the residual is recomputed in FP64 as b - A x ("reliable
+// update") and the inner residual restarted from it.
 // Convergence is always judged on that FP64 true residual.
 //
 // Scalars (alpha, beta, <r,r>) stay on the device; the host reads them only
@@ -34,15 +35,17 @@ namespace wd {
 size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
 // Plain FP64 CG keeps r, p, t, Ap in FP64 (the true-residual recompute reuses
-// r and t); mixed CG adds FP64 r and t.
+// r and t); mixed CG adds FP64 r and t and the FP32 solution accumulator.
 CgLayout cg_layout(long V, int slots, int inner) {
   CgLayout w;
   const size_t hi = align256(static_cast<size_t>(packed_sites(V)) * slots * spinor_site_bytes(WD_FP64));
   const size_t lo = align256(static_cast<size_t>(packed_sites(V)) * slots * spinor_site_bytes(inner));
+  const size_t acc = align256(static_cast<size_t>(packed_sites(V)) * slots * spinor_site_bytes(WD_FP32));
   size_t o = 0;
   if (inner != WD_FP64) {
     w.r_hi = o; o += hi;
     w.t_hi = o; o += hi;
+    w.x_lo = o; o += acc;
   }
   w.r = o; o += lo;
   w.p = o; o += lo;
@@ -83,6 +86,7 @@ CgEngine::CgEngine(const wd_gauge* ghi, const wd_gauge* glo, int inner, int slot
   nhi_ = packed_sites(V_) * 12;
   nlo_ = inner_ == WD_FP64 ? spinor_units<double>(V_)
                            : inner_ == WD_FP32 ? spinor_units<float>(V_) : spinor_units<_Float16>(V_);
+  n32_ = spinor_units<float>(V_);
   lay_ = cg_layout(V_, slots, inner_);
   partials_ = reinterpret_cast<double*>(at(ws_, lay_.partials));
   scal_ = reinterpret_cast<double*>(at(ws_, lay_.scal));
@@ -92,6 +96,8 @@ int CgEngine::start(const RhsSet& set, bool x0_given) {
   int rc = launch_status(blas_zero(scal_, WD_FP64, kScalars / 2, set, st_), "cg: scalars");
   if (rc == WD_OK)
     rc = launch_status(blas_norm2(b_, WD_FP64, nhi_, V_, set, partials_, scal_, kFinNorm, st_), "cg: |b|");
+  if (rc == WD_OK && inner_ != WD_FP64)
+    rc = launch_status(blas_zero(at(ws_, lay_.x_lo), WD_FP32, n32_, set, st_), "cg: x_lo");
   if (rc != WD_OK) return rc;
   if (x0_given) {
     rc = refresh(set);
@@ -122,8 +128,9 @@ int CgEngine::iterate(const RhsSet& set) {
     rc = launch_status(blas_norm2(at(ws_, lay_.t), inner_, nlo_, V_, set, partials_, scal_, kFinPap,
                                   st_), "cg: pAp");
   if (rc == WD_OK)
-    rc = launch_status(blas_update_xr(x_, at(ws_, lay_.r), at(ws_, lay_.p), at(ws_, lay_.ap), inner_,
-                                      nlo_, nhi_, V_, set, partials_, scal_, st_), "cg: x, r");
+    rc = launch_status(blas_update_xr(inner_ == WD_FP64 ? x_ : at(ws_, lay_.x_lo), at(ws_, lay_.r),
+                                      at(ws_, lay_.p), at(ws_, lay_.ap), inner_, nlo_, n32_, V_, set,
+                                      partials_, scal_, st_), "cg: x, r");
   if (rc == WD_OK)
     rc = launch_status(blas_update_p(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, V_, set, scal_, st_),
                        "cg: p");
@@ -133,8 +140,12 @@ int CgEngine::iterate(const RhsSet& set) {
 int CgEngine::refresh(const RhsSet& set) {
   double m[kMaxRhs];
   for (int i = 0; i < set.n; ++i) m[i] = masses_[set.idx[i]];
-  int rc = launch_status(launch_dslash_multi(ghi_, m, set.n, set.idx, x_, at(ws_, lay_.t_hi),
-                                             WD_FLAG_GAMMA5, st_), "cg: Q x");
+  int rc = WD_OK;
+  if (inner_ != WD_FP64)  // the FP32 accumulator joins the FP64 solution
+    rc = launch_status(blas_flush_x(x_, at(ws_, lay_.x_lo), n32_, nhi_, set, st_), "cg: flush x");
+  if (rc == WD_OK)
+    rc = launch_status(launch_dslash_multi(ghi_, m, set.n, set.idx, x_, at(ws_, lay_.t_hi),
+                                           WD_FLAG_GAMMA5, st_), "cg: Q x");
   if (rc == WD_OK)
     rc = launch_status(launch_dslash_multi(ghi_, m, set.n, set.idx, at(ws_, lay_.t_hi),
                                            at(ws_, lay_.r_hi), WD_FLAG_GAMMA5, st_), "cg: Q Q x");

@@ -12,7 +12,7 @@ namespace wd {
 // Offsets (bytes) of a CG workspace for `slots` right-hand sides.
 struct CgLayout {
   size_t bytes = 0;
-  size_t r_hi = 0, t_hi = 0, r = 0, p = 0, t = 0, ap = 0, partials = 0, scal = 0;
+  size_t r_hi = 0, t_hi = 0, x_lo = 0, r = 0, p = 0, t = 0, ap = 0, partials = 0, scal = 0;
 };
 CgLayout cg_layout(long V, int slots, int inner);
 
@@ -44,7 +44,8 @@ class CgEngine {
   int start(const RhsSet& set, bool x0_given);
   // one CG iteration on the slots of set
   int iterate(const RhsSet& set);
-  // FP64 true residual r = b - A x; inner residual restarted from it
+  // (mixed precision: x += x_lo, x_lo = 0) FP64 true residual r = b - A x;
+  // inner residual restarted from it
   int refresh(const RhsSet& set);
   // copies the scalars of every slot to host memory (async; pinned memory
   // for a true overlap)
@@ -59,7 +60,7 @@ class CgEngine {
   void* x_;
   void* ws_;
   hipStream_t st_;
-  long V_ = 0, nhi_ = 0, nlo_ = 0;
+  long V_ = 0, nhi_ = 0, nlo_ = 0, n32_ = 0;
   CgLayout lay_;
   double* partials_ = nullptr;
   double* scal_ = nullptr;
