@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define WD_ABI_VERSION 2
+#define WD_ABI_VERSION 3
 
 #if defined(__GNUC__)
 #define WD_API __attribute__((visibility("default")))
@@ -295,6 +295,8 @@ typedef struct wd_server_cfg {
   double delta;               /* reliable-update threshold (mixed precision), in (0, 1) */
   int32_t max_rhs_per_group;  /* 1..16 slots per group; also the largest nrhs of a request */
   int32_t n_streams;          /* 1..16 streams the groups are spread over */
+  int32_t evict_idle_gauges;  /* nonzero: wd_server_add_gauge evicts idle gauge fields (least
+                                 recently used first) when the arena has no room */
 } wd_server_cfg;
 
 typedef struct wd_request {
@@ -319,6 +321,8 @@ typedef struct wd_server_state {
   size_t arena_peak;     /* most bytes allocated at once so far */
   int32_t unfinished;    /* submitted requests not yet complete */
   int32_t gauges;        /* registered gauge fields */
+  int32_t evictions;     /* gauge fields evicted to make room so far */
+  int32_t reserved;
 } wd_server_state;
 
 /* Creates a server on the current device with its scheduler thread. The
@@ -326,8 +330,13 @@ typedef struct wd_server_state {
 WD_API int wd_server_create(const wd_server_cfg* cfg, wd_server** out);
 
 /* Packs the canonical complex128 gauge field U_canon_dev (FP64, plus a copy in
- * the inner precision for mixed precision) into the arena and returns its id; U_canon_dev is not
- * kept. Synchronous. WD_ERR_NOMEM if the arena has no room. */
+ * the inner precision for mixed precision) into the arena and returns its id;
+ * U_canon_dev is not kept. Synchronous. If the arena has no room and
+ * cfg.evict_idle_gauges is set, idle gauge fields (no request queued or
+ * running on them) are evicted, least recently used (registered or named by
+ * a request) first, until it fits; the id of an evicted field becomes unknown
+ * (cg_submit returns WD_ERR_INVALID_ARG; register it again). WD_ERR_NOMEM if
+ * the field cannot fit. */
 WD_API int wd_server_add_gauge(wd_server* s, const int32_t dims[4], const void* U_canon_dev,
                                uint64_t* gauge_id);
 

@@ -100,6 +100,7 @@ struct GaugeEntry {
   int groups = 0;    // groups currently built on it
   int requests = 0;  // queued or running requests on it
   bool removing = false;
+  double last_used = 0;  // server time of its registration or latest request
 };
 
 struct Request {
@@ -152,6 +153,7 @@ struct wd_server {
   std::thread worker;
   bool stop = false;
   uint64_t next_ticket = 1, next_gauge = 1;
+  int evictions = 0;
   std::map<uint64_t, std::unique_ptr<wd::GaugeEntry>> gauges;
   std::deque<wd::Request*> submitted;                       // not yet seen by the scheduler
   std::map<uint64_t, std::unique_ptr<wd::Request>> requests;  // every unpolled request
@@ -544,6 +546,25 @@ int wd_server_add_gauge(wd_server* s, const int32_t dims[4], const void* U_canon
     {
       std::lock_guard<std::mutex> lk(s->mu);
       ge->mem = s->arena.alloc(bhi + blo);
+      // with eviction on, idle gauge fields (no request queued or running, no
+      // group built on them, so no device work uses them) make room, least
+      // recently used first
+      while (ge->mem == nullptr && s->cfg.evict_idle_gauges) {
+        GaugeEntry* lru = nullptr;
+        for (auto& kv : s->gauges) {
+          GaugeEntry* g = kv.second.get();
+          if (!g->removing && g->requests == 0 && g->groups == 0 &&
+              (lru == nullptr || g->last_used < lru->last_used))
+            lru = g;
+        }
+        if (lru == nullptr) break;
+        wd_gauge_release(lru->hi);
+        wd_gauge_release(lru->lo);
+        s->arena.release(lru->mem);
+        s->gauges.erase(lru->id);
+        s->evictions++;
+        ge->mem = s->arena.alloc(bhi + blo);
+      }
     }
     if (ge->mem == nullptr) return set_error(WD_ERR_NOMEM, "arena has no room for the gauge field");
     hipStream_t st = nullptr;
@@ -569,6 +590,7 @@ int wd_server_add_gauge(wd_server* s, const int32_t dims[4], const void* U_canon
     ge->V = V;
     std::lock_guard<std::mutex> lk(s->mu);
     ge->id = s->next_gauge++;
+    ge->last_used = s->now();
     *gauge_id = ge->id;
     s->gauges[ge->id] = std::move(ge);
     return WD_OK;
@@ -636,6 +658,7 @@ int cg_submit(wd_server* s, const wd_request* req, uint64_t* ticket) {
     rq->ticket = s->next_ticket++;
     *ticket = rq->ticket;
     ge->requests++;
+    ge->last_used = s->now();
     s->running.fetch_add(1);
     s->submitted.push_back(rq.get());
     s->requests[rq->ticket] = std::move(rq);
@@ -681,6 +704,8 @@ int wd_server_info(wd_server* s, wd_server_state* out) {
   out->arena_peak = s->arena.peak();
   out->unfinished = s->running.load();
   out->gauges = static_cast<int32_t>(s->gauges.size());
+  out->evictions = s->evictions;
+  out->reserved = 0;
   return WD_OK;
 }
 

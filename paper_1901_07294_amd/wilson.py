@@ -36,7 +36,7 @@ WD_FP16 = 2
 
 WD_FLAG_GAMMA5 = 1
 
-ABI_VERSION = 2  # the structures below match this version of include/wilson.h
+ABI_VERSION = 3  # the structures below match this version of include/wilson.h
 
 STATUS_NAMES = {v: k for k, v in dict(globals()).items()
                 if k.startswith("WD_ERR_") or k in ("WD_OK", "WD_PENDING")}
@@ -70,7 +70,8 @@ class wd_tune_result(ctypes.Structure):
 class wd_server_cfg(ctypes.Structure):
     _fields_ = [("arena_dev", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
                 ("inner", ctypes.c_int32), ("check_every", ctypes.c_int32), ("delta", ctypes.c_double),
-                ("max_rhs_per_group", ctypes.c_int32), ("n_streams", ctypes.c_int32)]
+                ("max_rhs_per_group", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("evict_idle_gauges", ctypes.c_int32)]
 
 
 class wd_request(ctypes.Structure):
@@ -92,7 +93,8 @@ class wd_result(ctypes.Structure):
 
 class wd_server_state(ctypes.Structure):
     _fields_ = [("arena_in_use", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t),
-                ("unfinished", ctypes.c_int32), ("gauges", ctypes.c_int32)]
+                ("unfinished", ctypes.c_int32), ("gauges", ctypes.c_int32),
+                ("evictions", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 # Exported C symbols and their ctypes signatures.
@@ -310,10 +312,11 @@ def cg_solve_normal(g_hi, g_lo, masses, nrhs, b, x, params, ws, ws_bytes=None, s
 
 
 def wd_server_create(arena, inner, check_every=8, delta=0.1, max_rhs_per_group=16, n_streams=4,
-                     arena_bytes=None) -> int:
+                     arena_bytes=None, evict_idle_gauges=False) -> int:
     """Returns the server handle (an integer address)."""
     nb = _nbytes(arena) if arena_bytes is None else int(arena_bytes)
-    cfg = wd_server_cfg(_ptr(arena), nb, inner, check_every, delta, max_rhs_per_group, n_streams)
+    cfg = wd_server_cfg(_ptr(arena), nb, inner, check_every, delta, max_rhs_per_group, n_streams,
+                        int(bool(evict_idle_gauges)))
     out = ctypes.c_void_p()
     _check("wd_server_create", _L().wd_server_create(ctypes.byref(cfg), ctypes.byref(out)))
     return out.value
@@ -359,7 +362,7 @@ def wd_server_info(server) -> dict:
     st = wd_server_state()
     _check("wd_server_info", _L().wd_server_info(server, ctypes.byref(st)))
     return {"arena_in_use": st.arena_in_use, "arena_peak": st.arena_peak,
-            "unfinished": st.unfinished, "gauges": st.gauges}
+            "unfinished": st.unfinished, "gauges": st.gauges, "evictions": st.evictions}
 
 
 def wd_server_destroy(server) -> int:

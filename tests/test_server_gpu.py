@@ -199,3 +199,47 @@ def test_server_rejects_group_that_cannot_fit():
         assert e.value.code == w.WD_ERR_NOMEM
     finally:
         w.wd_server_destroy(srv)
+
+
+@pytest.mark.parametrize("evict", [False, True])
+def test_server_evicts_least_recently_used_idle_gauge(evict):
+    dims = (8, 8, 8, 8)
+    lats = [Lattice(dims, 1101 + i) for i in range(4)]
+    gauge = w.wd_gauge_bytes(dims, w.WD_FP64, 0) + w.wd_gauge_bytes(dims, w.WD_FP16, 0)
+    group = 2 * w.wd_spinor_bytes(dims, w.WD_FP64, 1) + w.cg_workspace_bytes(dims, 1, w.WD_FP16)
+    assert group > gauge
+    arena_bytes = 2 * gauge + group + (64 << 10)
+    srv, arena = make_server(arena_bytes, inner=w.WD_FP16, check_every=4, max_rhs_per_group=1,
+                             n_streams=1, evict_idle_gauges=evict)
+    try:
+        a = w.wd_server_add_gauge(srv, dims, lats[0].Ud)
+        b = w.wd_server_add_gauge(srv, dims, lats[1].Ud)
+        src = li.gaussian_spinor(dims, 77)
+        bd, x = lats[0].packer.pack(src), lats[0].packer.spinor(1)
+        t = w.cg_submit(srv, a, [0.2], bd, x)            # a becomes the most recently used
+        assert wait_all(srv, [t])[t][0] == w.WD_OK
+        t0 = time.time()
+        while w.wd_server_info(srv)["arena_in_use"] > 2 * gauge:   # its group is freed
+            assert time.time() - t0 < DEADLINE_S
+            time.sleep(0.005)
+        c = w.wd_server_add_gauge(srv, dims, lats[2].Ud)  # fits where the group was
+        assert w.wd_server_info(srv)["evictions"] == 0
+        if not evict:
+            with pytest.raises(w.WilsonError) as e:
+                w.wd_server_add_gauge(srv, dims, lats[3].Ud)
+            assert e.value.code == w.WD_ERR_NOMEM
+            return
+        d = w.wd_server_add_gauge(srv, dims, lats[3].Ud)  # evicts b, the least recently used
+        info = w.wd_server_info(srv)
+        assert info["evictions"] == 1 and info["gauges"] == 3
+        with pytest.raises(w.WilsonError) as e:
+            w.cg_submit(srv, b, [0.2], bd, x)
+        assert e.value.code == w.WD_ERR_INVALID_ARG
+        w.wd_server_remove_gauge(srv, c)                  # room for a group beside a and d
+        src_d = li.gaussian_spinor(dims, 78)
+        bd_d, x_d = lats[3].packer.pack(src_d), lats[3].packer.spinor(1)
+        t = w.cg_submit(srv, d, [0.2], bd_d, x_d)
+        assert wait_all(srv, [t])[t][0] == w.WD_OK
+        assert true_rel_residual(lats[3].U, 0.2, src_d, lats[3].packer.unpack(x_d)) <= 1e-10
+    finally:
+        w.wd_server_destroy(srv)
