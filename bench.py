@@ -128,6 +128,33 @@ def time_applies(torch, w, g, src, dst, mass, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms per apply
 
 
+def bench_latency(torch, w, li, DeviceGauge, oracle, n=1000):
+    """The smallest configuration, 4^4 FP64 with random SU(3) links: launch
+    latency of one dslash_apply (median of n individually timed launches) and
+    its parity against the oracle. Cache-resident; not a bandwidth figure."""
+    dims = (4, 4, 4, 4)
+    U = li.random_gauge(dims, li.seed_gauge(1))
+    psi = li.gaussian_spinor(dims, li.seed_spinor(1))
+    g = DeviceGauge(U, w.WD_FP64)
+    src, dst = g.pack(psi), g.spinor()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for _ in range(20):
+        w.dslash_apply(g.handle, 0.1, src, dst, g.prec)
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        w.dslash_apply(g.handle, 0.1, src, dst, g.prec)
+        b.record()
+    torch.cuda.synchronize()
+    us = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
+    ref = oracle.dslash(U, psi, 0.1)
+    err = float(np.linalg.norm(g.unpack(dst) - ref) / np.linalg.norm(ref))
+    return {"workload": "wilson_dslash_4x4x4x4_fp64", "launches": n,
+            "median_us": round(float(np.median(us)), 2), "p10_us": round(float(np.percentile(us, 10)), 2),
+            "p90_us": round(float(np.percentile(us, 90)), 2), "parity_rel_err": err,
+            "parity_ok": err <= 1e-13}
+
+
 def bench_multi(torch, w, li, DeviceGauge, prec="fp32", steps=50, warmup=5, inputs=None):
     """12 right-hand sides on 24^3 x 48, near-unity links, FP32 or FP16 storage:
     one fused launch against 12 single launches."""
@@ -170,7 +197,7 @@ def bench_multi(torch, w, li, DeviceGauge, prec="fp32", steps=50, warmup=5, inpu
             "tuning": tuned}
 
 
-def bench_cg(torch, w, li, DeviceGauge, reps=3):
+def bench_cg(torch, w, li, DeviceGauge, reps=3, cpu=True):
     """Solves of D^dag D x = b on 24^4, m = 0.05, near-unity links, to a true
     residual of 1e-10: plain FP64 CG against FP32 or FP16-storage inner
     iterations with FP64 reliable updates, eager and with chunks of iterations
@@ -209,10 +236,30 @@ def bench_cg(torch, w, li, DeviceGauge, reps=3):
     lat = setup(dims)
     out = {"workload": "cg_normal_24x24x24x24_m0.05", "tol": 1e-10, "gauge": "near-unity eps=0.3",
            "check_every": 8}
+    if cpu:
+        # the oracle's CG (FP64 numpy, one core) timed over 5 iterations and
+        # extrapolated to the GPU FP64 solver's iteration count
+        import oracle
+        U = li.near_unity_gauge(dims, li.seed_gauge(4), 0.3)
+        b = li.gaussian_spinor(dims, li.seed_spinor(4))
+        t0 = time.perf_counter()
+        oracle.normal_op(U, m, b)
+        t_op = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.cg_normal(U, m, b, tol=1e-10, max_iter=5)
+        t5 = time.perf_counter() - t0
+        out["cpu_oracle"] = {"kind": "oracle", "cores": 1, "label": "extrapolated",
+                             "s_per_iteration": round((t5 - t_op) / 5, 3), "s_setup": round(t_op, 3)}
+        del U, b
     for name, inner, graph in (("fp64", w.WD_FP64, 0), ("mixed_fp32", w.WD_FP32, 0),
                                ("mixed_fp16", w.WD_FP16, 0), ("fp64_graph", w.WD_FP64, 1),
                                ("mixed_fp32_graph", w.WD_FP32, 1), ("mixed_fp16_graph", w.WD_FP16, 1)):
         out[name] = run(dims, lat, inner, graph)
+    if "cpu_oracle" in out:
+        c = out["cpu_oracle"]
+        c["iterations"] = out["fp64"]["iters"]
+        c["s_per_solve"] = round(c["s_setup"] + c["iterations"] * c["s_per_iteration"], 1)
+        c["solves_per_s"] = round(1.0 / c["s_per_solve"], 5)
     base = out["fp64"]["ms_per_solve"]
     for name in ("mixed_fp32", "mixed_fp16", "fp64_graph", "mixed_fp32_graph", "mixed_fp16_graph"):
         out[name]["speedup_vs_fp64"] = round(base / out[name]["ms_per_solve"], 3)
@@ -453,7 +500,9 @@ def main(argv=None):
     cg = None
     if not args.no_cg:
         print("[bench] CG 24^4", file=sys.stderr, flush=True)
-        cg = bench_cg(torch, w, li, DeviceGauge)
+        cg = bench_cg(torch, w, li, DeviceGauge, cpu=not args.no_cpu_baseline)
+    print("[bench] latency 4^4", file=sys.stderr, flush=True)
+    latency = bench_latency(torch, w, li, DeviceGauge, oracle)
 
     workload = "wilson_dslash_" + "x".join(map(str, dims))
     key = f"{workload}_{args.prec}{'_c12' if args.c12 else ''}"
@@ -504,6 +553,7 @@ def main(argv=None):
         "tuning": tuned,
         "torch_copy_gbs": round(copy_gbs, 1),
         "variants": variants,
+        "latency_4x4x4x4": latency,
         "multi_rhs": multi,
         "cg": cg,
         "serve": serve,
