@@ -37,10 +37,17 @@ enum : int { kFinPap = 0, kFinIterRr = 1, kFinTrueRr = 2, kFinNorm = 3 };
 // partial sums of a reduction depends only on the lattice and precision.
 hipError_t blas_norm2(const void* v, int prec, long n, long V, const RhsSet& set, double* partials,
                       double* scal, int mode, hipStream_t st);
-// x += alpha p, r -= alpha Ap: x is the FP64 solution for FP64 vectors, else
-// the FP32 accumulator x_lo (nlo32 16-byte FP32 elements per right-hand side).
+// Partial sums of |v|^2 only (*nparts per right-hand side), for a following
+// kernel that reduces them itself.
+hipError_t blas_norm2_partials(const void* v, int prec, long n, long V, const RhsSet& set,
+                               double* partials, int* nparts, hipStream_t st);
+// x += alpha p, r -= alpha Ap with alpha = <r,r> / <p,Ap> reduced from the
+// npap partials in pap (written by blas_norm2_partials on Q p, a buffer other
+// than partials); x is the FP64 solution for FP64 vectors, else the FP32
+// accumulator x_lo (nlo32 16-byte FP32 elements per right-hand side).
 hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nlo32,
-                          long V, const RhsSet& set, double* partials, double* scal, hipStream_t st);
+                          long V, const RhsSet& set, const double* pap, int npap, double* partials,
+                          double* scal, hipStream_t st);
 // x_hi += x_lo, then x_lo = 0
 hipError_t blas_flush_x(void* hi, void* lo, long nlo32, long nhi, const RhsSet& set, hipStream_t st);
 hipError_t blas_update_p(void* p, const void* r, int prec, long n, long V, const RhsSet& set,

@@ -44,6 +44,36 @@ __device__ __forceinline__ double norm2(float4 a) {
   return fmar(x, x, fmar(y, y, fmar(z, z, w * w)));
 }
 
+// <p, A p> and alpha = <r, r> / <p, A p> from the partial sums of the
+// preceding norm kernel, computed by every workgroup in the same order (so
+// all agree bit for bit); workgroup 0 records them in the scalars.
+// Non-finite or non-positive curvature raises kFlag.
+__device__ __forceinline__ double alpha_from_partials(const double* __restrict__ pp, int np,
+                                                      double* sc) {
+  __shared__ double s_alpha;
+  double t = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) t += pp[i];
+  t = block_sum(t);
+  if (threadIdx.x == 0) {
+    bool flag = !isfinite(t);
+    double a;
+    if (!(t > 0.0)) {
+      a = 0.0;
+      if (sc[kRr] > 0.0) flag = true;
+    } else {
+      a = sc[kRr] / t;
+    }
+    if (blockIdx.x == 0) {
+      sc[kPap] = t;
+      sc[kAlpha] = a;
+      if (flag) sc[kFlag] = 1.0;
+    }
+    s_alpha = a;
+  }
+  __syncthreads();
+  return s_alpha;
+}
+
 // Is flat element e of a packed field of P elements per site a real site?
 template <int P>
 __device__ __forceinline__ bool real_site(long e, long V) {
@@ -85,11 +115,11 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void update_xr_kernel(T* __restrict__ x, T* __restrict__ r,
                                                              const T* __restrict__ p,
                                                              const T* __restrict__ ap, long n, long V,
-                                                             RhsSet set,
-                                                             const double* __restrict__ scal,
+                                                             RhsSet set, double* __restrict__ scal,
+                                                             const double* __restrict__ pap, int npap,
                                                              double* __restrict__ partials) {
   const int k = set.idx[blockIdx.y];
-  const double alpha = scal[k * kScalars + kAlpha];
+  const double alpha = alpha_from_partials(pap + k * npap, npap, scal + k * kScalars);
   T* xk = x + k * n;
   T* rk = r + k * n;
   const T* pk = p + k * n;
@@ -294,10 +324,10 @@ __global__ __launch_bounds__(kThreads) void norm2_half_kernel(const h8* __restri
 // requantised) ; partial |r|^2
 __global__ __launch_bounds__(kThreads) void update_xr_half_kernel(
     float4* __restrict__ x, h8* __restrict__ r, const h8* __restrict__ p, const h8* __restrict__ ap,
-    long units, long nlo32, long V, RhsSet set, const double* __restrict__ scal,
-    double* __restrict__ partials) {
+    long units, long nlo32, long V, RhsSet set, double* __restrict__ scal,
+    const double* __restrict__ pap, int npap, double* __restrict__ partials) {
   const int k = set.idx[blockIdx.y];
-  const float a = static_cast<float>(scal[k * kScalars + kAlpha]);
+  const float a = static_cast<float>(alpha_from_partials(pap + k * npap, npap, scal + k * kScalars));
   float4* xk = x + k * nlo32;
   h8* rk = r + k * units;
   double s = 0.0;
@@ -410,34 +440,44 @@ dim3 grid(long n, int nset) {
 
 hipError_t blas_norm2(const void* v, int prec, long n, long V, const RhsSet& set, double* partials,
                       double* scal, int mode, hipStream_t st) {
+  int np = 0;
+  const hipError_t e = blas_norm2_partials(v, prec, n, V, set, partials, &np, st);
+  if (e != hipSuccess) return e;
+  finalize_kernel<<<set.n, kThreads, 0, st>>>(partials, np, set, mode, scal);
+  return hipGetLastError();
+}
+
+hipError_t blas_norm2_partials(const void* v, int prec, long n, long V, const RhsSet& set,
+                               double* partials, int* nparts, hipStream_t st) {
   const dim3 g = grid(prec == WD_FP16 ? V : n, set.n);
+  *nparts = static_cast<int>(g.x);
   if (prec == WD_FP64)
     norm2_partial_kernel<double2><<<g, kThreads, 0, st>>>(static_cast<const double2*>(v), n, V, set, partials);
   else if (prec == WD_FP32)
     norm2_partial_kernel<float4><<<g, kThreads, 0, st>>>(static_cast<const float4*>(v), n, V, set, partials);
   else
     norm2_half_kernel<<<g, kThreads, 0, st>>>(static_cast<const h8*>(v), n, V, set, partials);
-  finalize_kernel<<<set.n, kThreads, 0, st>>>(partials, static_cast<int>(g.x), set, mode, scal);
   return hipGetLastError();
 }
 
 hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nlo32,
-                          long V, const RhsSet& set, double* partials, double* scal, hipStream_t st) {
+                          long V, const RhsSet& set, const double* pap, int npap, double* partials,
+                          double* scal, hipStream_t st) {
   const dim3 g = grid(prec == WD_FP16 ? V : n, set.n);
   if (prec == WD_FP64)
     update_xr_kernel<double2><<<g, kThreads, 0, st>>>(static_cast<double2*>(x), static_cast<double2*>(r),
                                                        static_cast<const double2*>(p),
                                                        static_cast<const double2*>(ap), n, V, set,
-                                                       scal, partials);
+                                                       scal, pap, npap, partials);
   else if (prec == WD_FP32)
     update_xr_kernel<float4><<<g, kThreads, 0, st>>>(static_cast<float4*>(x), static_cast<float4*>(r),
                                                       static_cast<const float4*>(p),
                                                       static_cast<const float4*>(ap), n, V, set, scal,
-                                                      partials);
+                                                      pap, npap, partials);
   else
     update_xr_half_kernel<<<g, kThreads, 0, st>>>(static_cast<float4*>(x), static_cast<h8*>(r),
                                                   static_cast<const h8*>(p), static_cast<const h8*>(ap),
-                                                  n, nlo32, V, set, scal, partials);
+                                                  n, nlo32, V, set, scal, pap, npap, partials);
   finalize_kernel<<<set.n, kThreads, 0, st>>>(partials, static_cast<int>(g.x), set, kFinIterRr, scal);
   return hipGetLastError();
 }

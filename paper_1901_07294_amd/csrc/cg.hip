@@ -56,6 +56,7 @@ CgLayout cg_layout(long V, int slots, int inner) {
     w.t_hi = w.t;
   }
   w.partials = o; o += align256(static_cast<size_t>(slots) * kMaxPartials * sizeof(double));
+  w.pap = o; o += align256(static_cast<size_t>(slots) * kMaxPartials * sizeof(double));
   w.scal = o; o += align256(static_cast<size_t>(slots) * kScalars * sizeof(double));
   w.bytes = o;
   return w;
@@ -89,6 +90,7 @@ CgEngine::CgEngine(const wd_gauge* ghi, const wd_gauge* glo, int inner, int slot
   n32_ = spinor_units<float>(V_);
   lay_ = cg_layout(V_, slots, inner_);
   partials_ = reinterpret_cast<double*>(at(ws_, lay_.partials));
+  pap_ = reinterpret_cast<double*>(at(ws_, lay_.pap));
   scal_ = reinterpret_cast<double*>(at(ws_, lay_.scal));
 }
 
@@ -124,13 +126,15 @@ int CgEngine::iterate(const RhsSet& set) {
   if (rc == WD_OK)
     rc = launch_status(launch_dslash_multi(glo_, m, set.n, set.idx, at(ws_, lay_.t),
                                            at(ws_, lay_.ap), WD_FLAG_GAMMA5, st_), "cg: Q Q p");
+  // <p, A p> = |Q p|^2: partial sums here, reduced (with alpha) inside the x, r update
+  int npap = 0;
   if (rc == WD_OK)
-    rc = launch_status(blas_norm2(at(ws_, lay_.t), inner_, nlo_, V_, set, partials_, scal_, kFinPap,
-                                  st_), "cg: pAp");
+    rc = launch_status(blas_norm2_partials(at(ws_, lay_.t), inner_, nlo_, V_, set, pap_, &npap, st_),
+                       "cg: pAp");
   if (rc == WD_OK)
     rc = launch_status(blas_update_xr(inner_ == WD_FP64 ? x_ : at(ws_, lay_.x_lo), at(ws_, lay_.r),
                                       at(ws_, lay_.p), at(ws_, lay_.ap), inner_, nlo_, n32_, V_, set,
-                                      partials_, scal_, st_), "cg: x, r");
+                                      pap_, npap, partials_, scal_, st_), "cg: x, r");
   if (rc == WD_OK)
     rc = launch_status(blas_update_p(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, V_, set, scal_, st_),
                        "cg: p");

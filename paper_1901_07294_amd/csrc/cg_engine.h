@@ -12,7 +12,7 @@ namespace wd {
 // Offsets (bytes) of a CG workspace for `slots` right-hand sides.
 struct CgLayout {
   size_t bytes = 0;
-  size_t r_hi = 0, t_hi = 0, x_lo = 0, r = 0, p = 0, t = 0, ap = 0, partials = 0, scal = 0;
+  size_t r_hi = 0, t_hi = 0, x_lo = 0, r = 0, p = 0, t = 0, ap = 0, partials = 0, pap = 0, scal = 0;
 };
 CgLayout cg_layout(long V, int slots, int inner);
 
@@ -63,6 +63,7 @@ class CgEngine {
   long V_ = 0, nhi_ = 0, nlo_ = 0, n32_ = 0;
   CgLayout lay_;
   double* partials_ = nullptr;
+  double* pap_ = nullptr;
   double* scal_ = nullptr;
   double masses_[kMaxRhs] = {};
 };
