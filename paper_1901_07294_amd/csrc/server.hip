@@ -29,66 +29,13 @@
 
 #include "cg_engine.h"
 #include "fields.h"
+#include "server_policy.h"
 
 namespace wd {
 namespace {
 
 using Clock = std::chrono::steady_clock;
 constexpr int kStarveSkips = 64;  // scheduling rounds a request may be passed over
-
-// First-fit allocator over the caller's arena (offsets aligned to 256 B).
-class Arena {
- public:
-  void init(char* base, size_t bytes) {
-    base_ = base;
-    free_.clear();
-    if (bytes > 0) free_[0] = bytes;
-  }
-  char* alloc(size_t n) {
-    n = align256(n);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second < n) continue;
-      const size_t off = it->first, sz = it->second;
-      free_.erase(it);
-      if (sz > n) free_[off + n] = sz - n;
-      used_[off] = n;
-      in_use_ += n;
-      peak_ = std::max(peak_, in_use_);
-      return base_ + off;
-    }
-    return nullptr;
-  }
-  void release(char* p) {
-    if (p == nullptr) return;
-    const size_t off = static_cast<size_t>(p - base_);
-    auto it = used_.find(off);
-    if (it == used_.end()) return;
-    size_t start = off, size = it->second;
-    in_use_ -= size;
-    used_.erase(it);
-    auto next = free_.lower_bound(start);
-    if (next != free_.end() && next->first == start + size) {
-      size += next->second;
-      next = free_.erase(next);
-    }
-    if (next != free_.begin()) {
-      auto prev = std::prev(next);
-      if (prev->first + prev->second == start) {
-        start = prev->first;
-        size += prev->second;
-        free_.erase(prev);
-      }
-    }
-    free_[start] = size;
-  }
-  size_t in_use() const { return in_use_; }
-  size_t peak() const { return peak_; }
-
- private:
-  char* base_ = nullptr;
-  std::map<size_t, size_t> free_, used_;
-  size_t in_use_ = 0, peak_ = 0;
-};
 
 struct GaugeEntry {
   uint64_t id = 0;
@@ -112,6 +59,7 @@ struct Request {
   int remaining = 0;
   int skipped = 0;
   wd_cg_stats stats[kMaxRhs] = {};
+  int nrhs() const { return r.nrhs; }
 };
 
 struct Slot {
@@ -138,6 +86,8 @@ struct Group {
     for (const Slot& s : slots) n += s.req != nullptr;
     return n;
   }
+  int free_slots() const { return S - active(); }
+  bool ready() const { return phase == kReady; }
 };
 
 }  // namespace
@@ -265,55 +215,33 @@ void wd_server::destroy_group(size_t i) {
   groups.erase(groups.begin() + static_cast<long>(i));
 }
 
-// Admits waiting requests, in arrival order, into groups with free slots
-// (creating a group if the arena has room). A request that does not fit is
-// passed over; once passed over kStarveSkips times, nothing behind it is
-// admitted until it has been.
+// Admits waiting requests into groups (policy in server_policy.h): the right-hand
+// sides of an admitted request are copied into free slots and started.
 bool wd_server::admit() {
-  bool did = false;
-  std::vector<Request*> waiting;  // requests this scan has passed over so far
-  for (auto it = pending.begin(); it != pending.end();) {
-    Request* rq = *it;
-    Group* target = nullptr;
-    bool busy_group_has_room = false;
-    for (auto& g : groups) {
-      if (g->gauge != rq->gauge || g->S - g->active() < rq->r.nrhs) continue;
-      if (g->phase == Group::kReady) {
-        target = g.get();
-        break;
+  struct Ops {
+    wd_server* s;
+    Group* make_group(GaugeEntry* ge) { return s->make_group(ge); }
+    void place(Group* target, Request* rq) {
+      std::vector<int> ks;
+      const size_t field = static_cast<size_t>(packed_sites(rq->gauge->V)) * spinor_site_bytes(WD_FP64);
+      for (int k = 0; k < target->S && static_cast<int>(ks.size()) < rq->r.nrhs; ++k) {
+        if (target->slots[k].req != nullptr) continue;
+        const int j = static_cast<int>(ks.size());
+        target->slots[k] = Slot{rq, j, 0, 0};
+        target->eng->set_mass(k, rq->r.masses[j]);
+        if (hipMemcpyAsync(target->mem + k * field, static_cast<const char*>(rq->r.b_dev) + j * field,
+                           field, hipMemcpyDeviceToDevice, target->stream) != hipSuccess)
+          s->fatal = WD_ERR_DEVICE;
+        ks.push_back(k);
       }
-      busy_group_has_room = true;  // it takes the request at its next chunk boundary
+      if (target->eng->start(set_of(ks), false) != WD_OK) s->fatal = WD_ERR_DEVICE;
+      std::lock_guard<std::mutex> lk(s->mu);
+      rq->t_start = s->now();
     }
-    if (target == nullptr && !busy_group_has_room) target = make_group(rq->gauge);
-    if (target == nullptr) {
-      if (rq->skipped > kStarveSkips) break;  // starving: nothing behind it may overtake
-      waiting.push_back(rq);
-      ++it;
-      continue;
-    }
-    // copy the right-hand sides into free slots and start them
-    std::vector<int> ks;
-    const size_t field = static_cast<size_t>(packed_sites(rq->gauge->V)) * spinor_site_bytes(WD_FP64);
-    for (int k = 0; k < target->S && static_cast<int>(ks.size()) < rq->r.nrhs; ++k) {
-      if (target->slots[k].req != nullptr) continue;
-      const int j = static_cast<int>(ks.size());
-      target->slots[k] = Slot{rq, j, 0, 0};
-      target->eng->set_mass(k, rq->r.masses[j]);
-      if (hipMemcpyAsync(target->mem + k * field, static_cast<const char*>(rq->r.b_dev) + j * field,
-                         field, hipMemcpyDeviceToDevice, target->stream) != hipSuccess)
-        fatal = WD_ERR_DEVICE;
-      ks.push_back(k);
-    }
-    if (target->eng->start(set_of(ks), false) != WD_OK) fatal = WD_ERR_DEVICE;
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      rq->t_start = now();
-    }
-    for (Request* w : waiting) w->skipped++;
-    it = pending.erase(it);
-    did = true;
-  }
-  return did;
+  } ops{this};
+  std::vector<Group*> current;
+  for (auto& g : groups) current.push_back(g.get());
+  return admit_requests(pending, current, ops, kStarveSkips);
 }
 
 void wd_server::launch_chunk(Group& g) {
@@ -460,14 +388,12 @@ void wd_server::loop() {
           launch_chunk(*g);
           did = true;
         }
-      // free idle groups whose gauge has no queued request, so their arena
-      // memory can go to other lattices
+      // free idle groups that no admissible queued request wants, so their
+      // arena memory can go to other lattices
       for (size_t i = groups.size(); i-- > 0;) {
         Group& g = *groups[i];
         if (g.phase != Group::kReady || g.active() > 0) continue;
-        bool wanted = false;
-        for (Request* rq : pending) wanted |= rq->gauge == g.gauge;
-        if (!wanted) destroy_group(i);
+        if (!group_wanted(pending, g.gauge, kStarveSkips)) destroy_group(i);
       }
       // gauge fields removed by the client go once nothing uses them
       std::lock_guard<std::mutex> lk(mu);
