@@ -43,6 +43,11 @@ constexpr int kMarchMultiThreads = 768;     // lanes of a several-right-hand-sid
 constexpr int kMarchTargetThreads = WD_MARCH_THREADS;
 constexpr int kMarchWgPerCu = WD_MARCH_WG_PER_CU;
 constexpr int kNumCu = 256;
+// Waves of the t-marching kernel a CU holds at once, from the compiled
+// kernels' register use: 256 VGPRs in FP64 (one wave per SIMD), 146-168 with
+// FP32 arithmetic (three per SIMD).
+constexpr int kWavesPerCuFp64 = 4;
+constexpr int kWavesPerCuFp32 = 12;
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 
 // Workgroup -> tile of kBlock consecutive sites. Consecutive workgroups are
@@ -375,10 +380,14 @@ MarchParams march_params(const Geo& geo, size_t real_bytes, int nrhs) {
     p.gw = best;
   }
   const int planes = columns * (nrhs / p.gw);
-  // as many workgroups as fit on the chip at once (LDS decides how many per
-  // CU), without a second round, and at least 4 t steps per workgroup so the
-  // prologue of each march stays cheap; t steps split evenly
-  const int per_cu = static_cast<int>(kLdsBytes / (p.gw * lds1));
+  // as many workgroups as fit on the chip at once (LDS and registers decide
+  // how many per CU), without a second round, and at least 4 t steps per
+  // workgroup so the prologue of each march stays cheap; t steps split evenly
+  const int waves = (p.gw * n + 63) / 64;
+  const int by_regs = (real_bytes == 8 ? kWavesPerCuFp64 : kWavesPerCuFp32) / waves;
+  int per_cu = static_cast<int>(kLdsBytes / (p.gw * lds1));
+  per_cu = per_cu < by_regs ? per_cu : by_regs;
+  per_cu = per_cu > 1 ? per_cu : 1;
   const int slots = kNumCu * (per_cu < kMarchWgPerCu ? per_cu : kMarchWgPerCu);
   int nt = slots / planes;
   const int nt_max = geo.T / 4 > 1 ? geo.T / 4 : 1;
