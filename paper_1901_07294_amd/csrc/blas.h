@@ -26,11 +26,12 @@ enum : int {
   kRrTrue = 5,  // <r, r> of the last true residual
   kB2 = 6,      // <b, b>
   kFlag = 7,    // nonzero: a non-finite or non-positive quantity appeared
-  kScalars = 8
+  kRrPrev = 8,  // <r, r> before the current x, r update (beta's denominator)
+  kScalars = 10  // even: the scalars are cleared as 16-byte elements
 };
 
 // What a reduction's result updates (finalize modes).
-enum : int { kFinPap = 0, kFinIterRr = 1, kFinTrueRr = 2, kFinNorm = 3 };
+enum : int { kFinPap = 0, kFinTrueRr = 2, kFinNorm = 3 };
 
 // n: 16-byte elements per right-hand side of the vectors in precision prec;
 // nhi: FP64 elements per right-hand side; V: lattice sites. The number of
@@ -44,14 +45,17 @@ hipError_t blas_norm2_partials(const void* v, int prec, long n, long V, const Rh
 // x += alpha p, r -= alpha Ap with alpha = <r,r> / <p,Ap> reduced from the
 // npap partials in pap (written by blas_norm2_partials on Q p, a buffer other
 // than partials); x is the FP64 solution for FP64 vectors, else the FP32
-// accumulator x_lo (nlo32 16-byte FP32 elements per right-hand side).
+// accumulator x_lo (nlo32 16-byte FP32 elements per right-hand side). Leaves
+// the *nrr partial sums of the new <r,r> per right-hand side in partials.
 hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nlo32,
                           long V, const RhsSet& set, const double* pap, int npap, double* partials,
-                          double* scal, hipStream_t st);
+                          int* nrr, double* scal, hipStream_t st);
 // x_hi += x_lo, then x_lo = 0
 hipError_t blas_flush_x(void* hi, void* lo, long nlo32, long nhi, const RhsSet& set, hipStream_t st);
+// p = r + beta p with beta = <r,r>_new / <r,r>_old, <r,r>_new reduced from the
+// nrr partial sums blas_update_xr left in rr; also records the new <r,r>.
 hipError_t blas_update_p(void* p, const void* r, int prec, long n, long V, const RhsSet& set,
-                         const double* scal, hipStream_t st);
+                         const double* rr, int nrr, double* scal, hipStream_t st);
 hipError_t blas_residual(void* r, const void* b, long n, long V, const RhsSet& set, double* partials,
                          double* scal, hipStream_t st);
 // lo (FP32 or FP16) = hi (FP64)

@@ -66,12 +66,39 @@ __device__ __forceinline__ double alpha_from_partials(const double* __restrict__
     if (blockIdx.x == 0) {
       sc[kPap] = t;
       sc[kAlpha] = a;
+      sc[kRrPrev] = sc[kRr];
       if (flag) sc[kFlag] = 1.0;
     }
     s_alpha = a;
   }
   __syncthreads();
   return s_alpha;
+}
+
+// The new <r, r> from the partial sums of the preceding x, r update and
+// beta = <r,r>_new / <r,r>_old, computed by every workgroup in the same order
+// (the order a one-workgroup reduction would take); workgroup 0 records
+// <r,r>, its running maximum and beta. Only workgroup 0 writes the scalars,
+// and the others read kRrPrev alone, which this kernel does not write.
+__device__ __forceinline__ double beta_from_partials(const double* __restrict__ pp, int np,
+                                                     double* sc) {
+  __shared__ double s_beta;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) s += pp[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) {
+    const double old = sc[kRrPrev];
+    const double b = old > 0.0 ? s / old : 0.0;
+    if (blockIdx.x == 0) {
+      if (!isfinite(s)) sc[kFlag] = 1.0;
+      sc[kBeta] = b;
+      sc[kRr] = s;
+      if (s > sc[kRrMax]) sc[kRrMax] = s;
+    }
+    s_beta = b;
+  }
+  __syncthreads();
+  return s_beta;
 }
 
 // Is flat element e of a packed field of P elements per site a real site?
@@ -186,9 +213,10 @@ __global__ __launch_bounds__(kThreads) void flush_x_kernel(double2* __restrict__
 template <typename T>
 __global__ __launch_bounds__(kThreads) void update_p_kernel(T* __restrict__ p, const T* __restrict__ r,
                                                             long n, RhsSet set,
-                                                            const double* __restrict__ scal) {
+                                                            const double* __restrict__ rr, int nrr,
+                                                            double* __restrict__ scal) {
   const int k = set.idx[blockIdx.y];
-  const double beta = scal[k * kScalars + kBeta];
+  const double beta = beta_from_partials(rr + k * nrr, nrr, scal + k * kScalars);
   T* pk = p + k * n;
   const T* rk = r + k * n;
   for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
@@ -357,9 +385,10 @@ __global__ __launch_bounds__(kThreads) void update_xr_half_kernel(
 __global__ __launch_bounds__(kThreads) void update_p_half_kernel(h8* __restrict__ p,
                                                                  const h8* __restrict__ r, long units,
                                                                  long V, RhsSet set,
-                                                                 const double* __restrict__ scal) {
+                                                                 const double* __restrict__ rr, int nrr,
+                                                                 double* __restrict__ scal) {
   const int k = set.idx[blockIdx.y];
-  const float b = static_cast<float>(scal[k * kScalars + kBeta]);
+  const float b = static_cast<float>(beta_from_partials(rr + k * nrr, nrr, scal + k * kScalars));
   h8* pk = p + k * units;
   WD_SITE_LOOP(i, V) {
     cx<float> pv[12], rv[12];
@@ -413,11 +442,6 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(const double* __rest
         sc[kAlpha] = sc[kRr] / s;
       }
       break;
-    case kFinIterRr:  // iterated residual; beta = rr_new / rr
-      sc[kBeta] = sc[kRr] > 0.0 ? s / sc[kRr] : 0.0;
-      sc[kRr] = s;
-      if (s > sc[kRrMax]) sc[kRrMax] = s;
-      break;
     case kFinTrueRr:  // true residual after a reliable update
       sc[kRr] = s;
       sc[kRrMax] = s;
@@ -462,8 +486,9 @@ hipError_t blas_norm2_partials(const void* v, int prec, long n, long V, const Rh
 
 hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nlo32,
                           long V, const RhsSet& set, const double* pap, int npap, double* partials,
-                          double* scal, hipStream_t st) {
+                          int* nrr, double* scal, hipStream_t st) {
   const dim3 g = grid(prec == WD_FP16 ? V : n, set.n);
+  *nrr = static_cast<int>(g.x);
   if (prec == WD_FP64)
     update_xr_kernel<double2><<<g, kThreads, 0, st>>>(static_cast<double2*>(x), static_cast<double2*>(r),
                                                        static_cast<const double2*>(p),
@@ -478,7 +503,6 @@ hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int p
     update_xr_half_kernel<<<g, kThreads, 0, st>>>(static_cast<float4*>(x), static_cast<h8*>(r),
                                                   static_cast<const h8*>(p), static_cast<const h8*>(ap),
                                                   n, nlo32, V, set, scal, pap, npap, partials);
-  finalize_kernel<<<set.n, kThreads, 0, st>>>(partials, static_cast<int>(g.x), set, kFinIterRr, scal);
   return hipGetLastError();
 }
 
@@ -489,16 +513,17 @@ hipError_t blas_flush_x(void* hi, void* lo, long nlo32, long nhi, const RhsSet& 
 }
 
 hipError_t blas_update_p(void* p, const void* r, int prec, long n, long V, const RhsSet& set,
-                         const double* scal, hipStream_t st) {
+                         const double* rr, int nrr, double* scal, hipStream_t st) {
   if (prec == WD_FP64)
     update_p_kernel<double2><<<grid(n, set.n), kThreads, 0, st>>>(
-        static_cast<double2*>(p), static_cast<const double2*>(r), n, set, scal);
+        static_cast<double2*>(p), static_cast<const double2*>(r), n, set, rr, nrr, scal);
   else if (prec == WD_FP32)
     update_p_kernel<float4><<<grid(n, set.n), kThreads, 0, st>>>(
-        static_cast<float4*>(p), static_cast<const float4*>(r), n, set, scal);
+        static_cast<float4*>(p), static_cast<const float4*>(r), n, set, rr, nrr, scal);
   else
     update_p_half_kernel<<<grid(V, set.n), kThreads, 0, st>>>(static_cast<h8*>(p),
-                                                              static_cast<const h8*>(r), n, V, set, scal);
+                                                              static_cast<const h8*>(r), n, V, set, rr,
+                                                              nrr, scal);
   return hipGetLastError();
 }
 

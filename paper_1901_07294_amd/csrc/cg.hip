@@ -131,13 +131,15 @@ int CgEngine::iterate(const RhsSet& set) {
   if (rc == WD_OK)
     rc = launch_status(blas_norm2_partials(at(ws_, lay_.t), inner_, nlo_, V_, set, pap_, &npap, st_),
                        "cg: pAp");
+  // <r, r> likewise: partial sums in the x, r update, reduced (with beta) inside the p update
+  int nrr = 0;
   if (rc == WD_OK)
     rc = launch_status(blas_update_xr(inner_ == WD_FP64 ? x_ : at(ws_, lay_.x_lo), at(ws_, lay_.r),
                                       at(ws_, lay_.p), at(ws_, lay_.ap), inner_, nlo_, n32_, V_, set,
-                                      pap_, npap, partials_, scal_, st_), "cg: x, r");
+                                      pap_, npap, partials_, &nrr, scal_, st_), "cg: x, r");
   if (rc == WD_OK)
-    rc = launch_status(blas_update_p(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, V_, set, scal_, st_),
-                       "cg: p");
+    rc = launch_status(blas_update_p(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, V_, set, partials_,
+                                     nrr, scal_, st_), "cg: p");
   return rc;
 }
 
