@@ -290,12 +290,13 @@ def bench_cg(torch, w, li, DeviceGauge, reps=3, cpu=True):
     return out
 
 
-def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=30, loads=(0.5, 0.8, 0.95), seed=5000):
+def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=60, loads=(0.5, 0.8, 0.95), seed=5000,
+                arena_gib=128):
     """Request server under Poisson streams of CG solves (tol 1e-10, FP16-storage
     inner iterations with FP64 reliable updates) on a resident pool of two
     near-unity gauge fields per lattice size (8^4, 16^4, 24^3x48, 32^3x64);
-    1..12 right-hand sides per request, masses uniform in [0.05, 0.5].
-    Capacity is measured with a saturated queue, then latencies at each of
+    1..12 right-hand sides per request, masses uniform in [0.05, 0.5], in an
+    arena of `arena_gib` GiB (gauge fields and solve groups). Capacity is measured with a saturated queue, then latencies at each of
     `loads` times that rate; a second server with a small arena forces
     requests to queue."""
     import oracle
@@ -345,9 +346,13 @@ def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=30, loads=(0.5, 0
             x = lat[i]["packer"].spinor(len(m))
             t = w.cg_submit(srv, lat[i]["gid"], m, lat[i]["pool"], x, tol=1e-10)
             live[t] = (i, m, x)
-        deadline = time.time() + 600
+        deadline = time.time() + 120
+        note = time.time() + 30
         while live:
-            assert time.time() < deadline, "serving measurement timed out"
+            assert time.time() < deadline, f"serving measurement timed out ({len(live)} requests left)"
+            if time.time() > note:
+                print(f"[bench] serving: {len(live)} requests still running", file=sys.stderr, flush=True)
+                note += 30
             poll()
             time.sleep(0.0005)
         return done, time.time() - t0
@@ -369,14 +374,17 @@ def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=30, loads=(0.5, 0
         return round(float(np.percentile(v, q)) * 1e3, 2)
 
     out = {"workload": "cg_requests_8^4_16^4_24^3x48_32^3x64_poisson", "inner": "fp16+fp64_reliable",
-           "tol": 1e-10, "gauge_pool": "2 near-unity configs per size (seeds 5100..5107)"}
-    arena = torch.empty(48 << 30, dtype=torch.uint8, device="cuda")
+           "tol": 1e-10, "gauge_pool": "2 near-unity configs per size (seeds 5100..5107)",
+           "arena_gib": arena_gib}
+    torch.cuda.empty_cache()
+    arena = torch.empty(arena_gib << 30, dtype=torch.uint8, device="cuda")
     srv = w.wd_server_create(arena, w.WD_FP16, check_every=8, delta=0.1,
                              max_rhs_per_group=nrhs_max, n_streams=4)
     try:
         lat = make_pool(srv, sizes, 2)
         done, makespan = run_stream(srv, lat, [None] * n_closed, nrhs_max)
         capacity = n_closed / makespan
+        print(f"[bench] serving capacity {capacity:.2f} req/s", file=sys.stderr, flush=True)
         out["capacity_req_per_s"] = round(capacity, 3)
         out["levels"] = []
         worst = worst_residual(lat, done)
@@ -394,6 +402,9 @@ def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=30, loads=(0.5, 0
                 "p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99),
                 "queue_wait_p50_ms": pct(wait_s, 50), "queue_wait_p99_ms": pct(wait_s, 99)})
             worst = max(worst, worst_residual(lat, done))
+            lv = out["levels"][-1]
+            print(f"[bench] serving load {load}: p50 {lv['p50_ms']} ms, p99 {lv['p99_ms']} ms",
+                  file=sys.stderr, flush=True)
         out["max_true_rel_residual_small_lattices"] = worst
         out["arena_peak_gb"] = round(w.wd_server_info(srv)["arena_peak"] / 1e9, 2)
     finally:

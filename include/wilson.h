@@ -281,7 +281,9 @@ WD_API int cg_solve_normal(const wd_gauge* g_hi, const wd_gauge* g_lo, const dou
  * streams and overlap on the device. A right-hand side gets bit-identical
  * results alone or in any mix. Requests wait (first fit in arrival order,
  * with a bound on how often one can be passed over) until a group of their
- * gauge field has free slots or the arena has room for a new group.
+ * gauge field has free slots or the arena has room for a new group: one of
+ * max_rhs_per_group slots, or, when that does not fit, one of just the
+ * request's nrhs slots.
  * All server calls are thread-safe.
  * ------------------------------------------------------------------------ */
 
@@ -346,7 +348,9 @@ WD_API int wd_server_remove_gauge(wd_server* s, uint64_t gauge_id);
 
 /* Queues a solve and returns at once with a ticket. b_dev and x_dev are
  * caller-owned and must stay valid until cg_poll reports a final status
- * (b_dev is copied into the arena when the request is admitted). */
+ * (b_dev is copied into the arena when the request is admitted).
+ * WD_ERR_NOMEM if a group of the request's nrhs slots cannot fit in the arena
+ * beside the registered gauge fields. */
 WD_API int cg_submit(wd_server* s, const wd_request* req, uint64_t* ticket);
 
 /* WD_PENDING while the request is queued or running (out, if non-NULL, gets

@@ -123,7 +123,7 @@ struct wd_server {
   void launch_chunk(wd::Group& g);
   void finish_slot(wd::Group& g, int k, int status);
   void destroy_group(size_t i);
-  wd::Group* make_group(wd::GaugeEntry* ge);
+  wd::Group* make_group(wd::GaugeEntry* ge, int need);
   void complete(wd::Request* rq);
 };
 
@@ -168,13 +168,19 @@ void wd_server::complete(Request* rq) {
   running.fetch_sub(1);
 }
 
-Group* wd_server::make_group(GaugeEntry* ge) {
-  const int S = cfg.max_rhs_per_group;
-  const size_t bytes = group_bytes(ge->V, S, cfg.inner);
+// A group of the configured number of slots if the arena has room for one,
+// else one of just `need` slots (the request that asks for it), so that a
+// request does not wait for memory a smaller group would not need.
+Group* wd_server::make_group(GaugeEntry* ge, int need) {
+  int S = cfg.max_rhs_per_group;
   char* mem;
   {
     std::lock_guard<std::mutex> lk(mu);
-    mem = arena.alloc(bytes);
+    mem = arena.alloc(group_bytes(ge->V, S, cfg.inner));
+    if (mem == nullptr && need < S) {
+      S = need;
+      mem = arena.alloc(group_bytes(ge->V, S, cfg.inner));
+    }
   }
   if (mem == nullptr) return nullptr;
   auto g = std::make_unique<Group>();
@@ -220,7 +226,7 @@ void wd_server::destroy_group(size_t i) {
 bool wd_server::admit() {
   struct Ops {
     wd_server* s;
-    Group* make_group(GaugeEntry* ge) { return s->make_group(ge); }
+    Group* make_group(GaugeEntry* ge, int need) { return s->make_group(ge, need); }
     void place(Group* target, Request* rq) {
       std::vector<int> ks;
       const size_t field = static_cast<size_t>(packed_sites(rq->gauge->V)) * spinor_site_bytes(WD_FP64);
@@ -393,7 +399,7 @@ void wd_server::loop() {
       for (size_t i = groups.size(); i-- > 0;) {
         Group& g = *groups[i];
         if (g.phase != Group::kReady || g.active() > 0) continue;
-        if (!group_wanted(pending, g.gauge, kStarveSkips)) destroy_group(i);
+        if (!group_wanted(pending, g.gauge, g.S, kStarveSkips)) destroy_group(i);
       }
       // gauge fields removed by the client go once nothing uses them
       std::lock_guard<std::mutex> lk(mu);
@@ -563,14 +569,15 @@ int cg_submit(wd_server* s, const wd_request* req, uint64_t* ticket) {
     if (overlaps(req->b_dev, vec, req->x_dev, vec))
       return set_error(WD_ERR_INVALID_ARG, "b_dev and x_dev overlap");
     {
-      // the arena minus the registered gauge fields must hold one group
+      // the arena minus the registered gauge fields must hold a group of the
+      // request's right-hand sides
       size_t gauges = 0;
       lk.lock();
       for (auto& [id, g] : s->gauges)
         if (!g->removing)
           gauges += align256(wd_gauge_bytes(g->dims, WD_FP64, 0)) + inner_gauge_bytes(g->dims, s->cfg.inner);
       lk.unlock();
-      if (group_bytes(ge->V, s->cfg.max_rhs_per_group, s->cfg.inner) + gauges > s->cfg.arena_bytes)
+      if (group_bytes(ge->V, req->nrhs, s->cfg.inner) + gauges > s->cfg.arena_bytes)
         return set_error(WD_ERR_NOMEM, "a solve group of this lattice cannot fit beside the gauge fields");
     }
     auto rq = std::make_unique<Request>();

@@ -71,7 +71,8 @@ class Arena {
 
 // Admits queued requests, in arrival order, into groups of their gauge field
 // with enough free slots, creating a group when none exists and the arena has
-// room. A group that is running a chunk is not joined now, but a request it
+// room (the executor decides its size: at least the request's right-hand
+// sides). A group that is running a chunk is not joined now, but a request it
 // could take waits for it rather than opening a second group. A request that
 // cannot be placed is passed over (its `skipped` count grows each time a later
 // request is admitted before it); once passed over more than `starve_skips`
@@ -79,8 +80,9 @@ class Arena {
 // request was admitted.
 //
 // Req needs: gauge, nrhs(), skipped. Group needs: gauge, free_slots(), ready().
-// Ops needs: Group* make_group(gauge) (nullptr if it does not fit) and
-// void place(Group*, Req*) (assign slots and start them).
+// Ops needs: Group* make_group(gauge, need) (a group with at least `need`
+// slots, nullptr if none fits) and void place(Group*, Req*) (assign slots and
+// start them).
 template <class Req, class Group, class Ops>
 bool admit_requests(std::deque<Req*>& pending, const std::vector<Group*>& groups, Ops& ops,
                     int starve_skips) {
@@ -99,7 +101,7 @@ bool admit_requests(std::deque<Req*>& pending, const std::vector<Group*>& groups
         else busy_group_has_room = true;  // it takes the request at its next chunk boundary
       }
     if (target == nullptr && !busy_group_has_room) {
-      target = ops.make_group(rq->gauge);
+      target = ops.make_group(rq->gauge, rq->nrhs());
       if (target != nullptr) made.push_back(target);
     }
     if (target == nullptr) {
@@ -116,15 +118,18 @@ bool admit_requests(std::deque<Req*>& pending, const std::vector<Group*>& groups
   return did;
 }
 
-// Whether an idle group of `gauge` should be kept for a queued request. Only
-// requests that can be admitted count: those up to and including the first
-// starving one (nothing behind a starving request is admitted before it), so
-// that idle groups of other gauges give their memory to the starving request
-// instead of being held, forever, for requests queued behind it.
+// Whether an idle group of `gauge` with `slots` slots should be kept for a
+// queued request. Only requests that can be admitted count: those up to and
+// including the first starving one (nothing behind a starving request is
+// admitted before it), so that idle groups of other gauges give their memory
+// to the starving request instead of being held, forever, for requests queued
+// behind it; and only requests the group can hold, so that a group opened
+// small (for a request that found no room for a full one) gives its memory
+// back to the larger requests of its gauge.
 template <class Req, class Gauge>
-bool group_wanted(const std::deque<Req*>& pending, const Gauge& gauge, int starve_skips) {
+bool group_wanted(const std::deque<Req*>& pending, const Gauge& gauge, int slots, int starve_skips) {
   for (const Req* r : pending) {
-    if (r->gauge == gauge) return true;
+    if (r->gauge == gauge && r->nrhs() <= slots) return true;
     if (r->skipped > starve_skips) return false;
   }
   return false;

@@ -1,5 +1,5 @@
 """The request server's scheduling policy (arena allocator, admission,
-anti-starvation, release of idle groups) on the host, with a fake executor.
+anti-starvation, demand-sized groups, release of idle groups) on the host, with a fake executor.
 
 tests/scheduler_driver.cpp includes the policy header the server is built
 from and simulates groups whose chunks finish in one round; it is compiled
@@ -12,7 +12,8 @@ from pathlib import Path
 import pytest
 
 ROOT = Path(__file__).resolve().parents[1]
-SCENARIOS = ["arena", "fifo_join", "busy_group", "starvation", "serving"]
+SCENARIOS = (["arena", "fifo_join", "busy_group", "starvation", "small_groups", "small_idle_groups",
+              "serving"] + [f"serving_mix_{seed}" for seed in range(1, 21)])
 
 
 @pytest.fixture(scope="module")

@@ -243,3 +243,46 @@ def test_server_evicts_least_recently_used_idle_gauge(evict):
         assert true_rel_residual(lats[3].U, 0.2, src_d, lats[3].packer.unpack(x_d)) <= 1e-10
     finally:
         w.wd_server_destroy(srv)
+
+
+def test_server_opens_a_smaller_group_when_a_full_one_does_not_fit():
+    dims = (8, 8, 8, 8)
+    lats = [Lattice(dims, 1201), Lattice(dims, 1202)]
+    inner = w.WD_FP32
+    gauge = w.wd_gauge_bytes(dims, w.WD_FP64, 0) + w.wd_gauge_bytes(dims, inner, 0)
+
+    def group(S):
+        return 2 * w.wd_spinor_bytes(dims, w.WD_FP64, S) + w.cg_workspace_bytes(dims, S, inner)
+
+    # two gauge fields, one group of 4 slots and one of 1 (not 2)
+    arena_bytes = 2 * gauge + group(4) + group(1) + (64 << 10)
+    assert group(1) + (64 << 10) < group(2)
+    b_big = li.gaussian_spinors(dims, [1300 + k for k in range(4)])
+    b_one = li.gaussian_spinor(dims, 1310)
+
+    def run(with_big):
+        srv, arena = make_server(arena_bytes, inner=inner, check_every=4, max_rhs_per_group=4,
+                                 n_streams=2)
+        try:
+            ga = w.wd_server_add_gauge(srv, dims, lats[0].Ud)
+            gb = w.wd_server_add_gauge(srv, dims, lats[1].Ud)
+            tickets = []
+            if with_big:
+                bd_big, x_big = lats[0].packer.pack(b_big, nrhs=4), lats[0].packer.spinor(4)
+                tickets.append(w.cg_submit(srv, ga, [0.05, 0.1, 0.2, 0.3], bd_big, x_big, tol=1e-10))
+            bd_one, x_one = lats[1].packer.pack(b_one), lats[1].packer.spinor(1)
+            tickets.append(w.cg_submit(srv, gb, [0.07], bd_one, x_one, tol=1e-10))
+            done = wait_all(srv, tickets)
+            assert all(done[t][0] == w.WD_OK for t in tickets)
+            assert w.wd_server_info(srv)["arena_peak"] <= arena_bytes
+            res = {t: done[t][1] for t in tickets}
+            return res, tickets, lats[1].packer.unpack(x_one)
+        finally:
+            w.wd_server_destroy(srv)
+
+    res, (t_big, t_one), x = run(True)
+    # the 1-RHS request runs beside the 4-RHS one instead of waiting for its memory
+    assert res[t_one]["t_start"] < res[t_big]["t_done"]
+    assert true_rel_residual(lats[1].U, 0.07, b_one, x) <= 1e-10
+    _, _, x_alone = run(False)
+    assert np.array_equal(x, x_alone)
