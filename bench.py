@@ -290,15 +290,17 @@ def bench_cg(torch, w, li, DeviceGauge, reps=3, cpu=True):
     return out
 
 
-def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=60, loads=(0.5, 0.8, 0.95), seed=5000,
-                arena_gib=128):
+def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), seed=5000, arena_gib=128):
     """Request server under Poisson streams of CG solves (tol 1e-10, FP16-storage
     inner iterations with FP64 reliable updates) on a resident pool of two
     near-unity gauge fields per lattice size (8^4, 16^4, 24^3x48, 32^3x64);
     1..12 right-hand sides per request, masses uniform in [0.05, 0.5], in an
-    arena of `arena_gib` GiB (gauge fields and solve groups). Capacity is measured with a saturated queue, then latencies at each of
-    `loads` times that rate; a second server with a small arena forces
-    requests to queue."""
+    arena of `arena_gib` GiB (gauge fields and solve groups). One list of
+    `n_req` requests is drawn once: capacity is its makespan when all are
+    queued at once, then the same requests arrive as a Poisson stream (one
+    pattern of gaps, scaled) at each of `loads` times that rate, so the levels
+    differ only in load. A second server with a small arena forces requests to
+    queue."""
     import oracle
     from paper_1901_07294_amd.buffers import to_device
     sizes = [(8, 8, 8, 8), (16, 16, 16, 16), (24, 24, 24, 48), (32, 32, 32, 64)]
@@ -327,8 +329,9 @@ def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=60, loads=(0.5, 0
         nrhs = int(rng.integers(1, max_rhs + 1))
         return i, list(rng.uniform(0.05, 0.5, nrhs))
 
-    def run_stream(srv, lat, arrivals, max_rhs):
-        """Submits at the given times (s; None = all at once); returns {ticket: (rc, res, req)}."""
+    def run_stream(srv, lat, reqs, arrivals):
+        """Submits reqs[k] = (pool index, masses) at arrivals[k] (s; None = at once);
+        returns {ticket: (rc, res, (pool index, masses, x))} and the makespan."""
         live, done = {}, {}
 
         def poll():
@@ -338,11 +341,10 @@ def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=60, loads=(0.5, 0
                     done[t] = (rc, res, live.pop(t))
 
         t0 = time.time()
-        for a in arrivals:
+        for (i, m), a in zip(reqs, arrivals):
             while a is not None and time.time() - t0 < a:
                 poll()
                 time.sleep(0.0005)
-            i, m = draw(lat, max_rhs)
             x = lat[i]["packer"].spinor(len(m))
             t = w.cg_submit(srv, lat[i]["gid"], m, lat[i]["pool"], x, tol=1e-10)
             live[t] = (i, m, x)
@@ -382,24 +384,28 @@ def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=60, loads=(0.5, 0
                              max_rhs_per_group=nrhs_max, n_streams=4)
     try:
         lat = make_pool(srv, sizes, 2)
-        done, makespan = run_stream(srv, lat, [None] * n_closed, nrhs_max)
-        capacity = n_closed / makespan
+        reqs = [draw(lat, nrhs_max) for _ in range(n_req)]
+        gaps = rng.exponential(1.0, n_req)  # unit-rate Poisson gaps, scaled per level
+        nrhs_total = sum(len(m) for _, m in reqs)
+        done, makespan = run_stream(srv, lat, reqs, [None] * n_req)
+        capacity = n_req / makespan
         print(f"[bench] serving capacity {capacity:.2f} req/s", file=sys.stderr, flush=True)
+        out["requests"] = n_req
+        out["rhs_per_request_mean"] = round(nrhs_total / n_req, 2)
         out["capacity_req_per_s"] = round(capacity, 3)
+        out["capacity_rhs_solves_per_s"] = round(nrhs_total / makespan, 2)
         out["levels"] = []
         worst = worst_residual(lat, done)
         for load in loads:
-            lam = load * capacity
-            arrivals = list(np.cumsum(rng.exponential(1.0 / lam, n_open)))
-            done, wall = run_stream(srv, lat, arrivals, nrhs_max)
+            arrivals = list(np.cumsum(gaps / (load * capacity)))
+            done, wall = run_stream(srv, lat, reqs, arrivals)
             lat_s = np.array([res["t_done"] - res["t_submit"] for rc, res, _ in done.values()])
             wait_s = np.array([res["t_start"] - res["t_submit"] for rc, res, _ in done.values()])
-            nrhs_total = sum(len(v[2][1]) for v in done.values())
             out["levels"].append({
-                "offered_load": load, "requests": n_open,
+                "offered_load": load, "requests": n_req,
                 "ok": int(sum(rc == w.WD_OK for rc, _, _ in done.values())),
-                "req_per_s": round(n_open / wall, 3), "rhs_solves_per_s": round(nrhs_total / wall, 2),
-                "p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99),
+                "req_per_s": round(n_req / wall, 3), "rhs_solves_per_s": round(nrhs_total / wall, 2),
+                "p50_ms": pct(lat_s, 50), "p90_ms": pct(lat_s, 90), "p99_ms": pct(lat_s, 99),
                 "queue_wait_p50_ms": pct(wait_s, 50), "queue_wait_p99_ms": pct(wait_s, 99)})
             worst = max(worst, worst_residual(lat, done))
             lv = out["levels"][-1]
@@ -422,7 +428,7 @@ def bench_serve(torch, w, li, DeviceGauge, n_closed=12, n_open=60, loads=(0.5, 0
                              n_streams=2)
     try:
         lat = make_pool(srv, small_sizes, 2)
-        done, wall = run_stream(srv, lat, [None] * 16, 4)
+        done, wall = run_stream(srv, lat, [draw(lat, 4) for _ in range(16)], [None] * 16)
         wait_s = np.array([res["t_start"] - res["t_submit"] for rc, res, _ in done.values()])
         info = w.wd_server_info(srv)
         out["small_arena"] = {
