@@ -208,7 +208,17 @@ def bench_multi(torch, w, li, DeviceGauge, prec="fp32", steps=50, warmup=5, inpu
     tune(torch, w, g, 1, one)
     single = timed(lambda: w.dslash_apply(g.handle, 0.1, one, res, g.prec)) * nrhs
     comp = REAL_BYTES[prec] * 4 * 18 + nrhs * 2 * SPINOR_BYTES[prec]  # links once + 12 x (in + out)
+    # parity of the fused launch's output against the oracle on sampled sites of every field
+    import oracle
+    outs = g.unpack(dst, nrhs=nrhs).reshape(nrhs, -1, 4, 3)
+    sites = np.random.default_rng(8).choice(V, 256, replace=False)
+    err = 0.0
+    for k in range(nrhs):
+        ref = oracle.dslash_sites(U, psis[k], masses[k], sites)
+        err = max(err, float(np.linalg.norm(outs[k][sites] - ref) / np.linalg.norm(ref)))
+    tol = {"fp32": 1e-6, "fp16": 2e-3}[prec]
     return {"workload": "wilson_dslash_multi_24x24x24x48_x12", "prec": prec, "links": "full",
+            "parity": {"max_rel_err": err, "tol": tol, "sites_per_field": 256, "ok": err <= tol},
             "gauge": "near-unity eps=0.3", "ms_per_apply": round(fused, 4),
             "gflops": round(nrhs * FLOPS_PER_SITE * V / (fused / 1e3) / 1e9, 1),
             "pct_hbm_peak": round(100 * comp * V / (fused / 1e3) / 1e9 / HBM_PEAK_GBS, 2),
@@ -221,8 +231,12 @@ def bench_cg(torch, w, li, DeviceGauge, reps=3, cpu=True):
     residual of 1e-10: plain FP64 CG against FP32 or FP16-storage inner
     iterations with FP64 reliable updates, eager and with chunks of iterations
     replayed as HIP graphs; and the same eager/graph pair on an 8^4 lattice,
-    where launch overhead dominates."""
+    where launch overhead dominates. Every solution is checked outside the
+    timed region by the oracle: its true residual |b - D^dag D x| / |b|
+    recomputed in FP64 on the CPU, and its distance from the FP64 solve's x."""
+    import oracle
     m = 0.05
+    x_fp64 = {}
 
     def setup(dims):
         U = li.near_unity_gauge(dims, li.seed_gauge(4), 0.3)
@@ -230,10 +244,27 @@ def bench_cg(torch, w, li, DeviceGauge, reps=3, cpu=True):
         ghi = DeviceGauge(U, w.WD_FP64)
         glo = {w.WD_FP64: ghi, w.WD_FP32: DeviceGauge(U, w.WD_FP32),
                w.WD_FP16: DeviceGauge(U, w.WD_FP16)}
-        return ghi, glo, ghi.pack(b), ghi.spinor(1), b
+        return ghi, glo, ghi.pack(b), ghi.spinor(1), b, U
+
+    x_eager = {}
+
+    def check(dims, lat, inner, use_graph):
+        ghi, _, _, x, b, U = lat
+        xs = ghi.unpack(x)
+        if use_graph and (dims, inner) in x_eager:  # graph replay: the eager solve's bits
+            return {"same_x_as_eager": bool(np.array_equal(xs, x_eager[(dims, inner)]))}
+        x_eager[(dims, inner)] = xs
+        r = b - oracle.normal_op(U, m, xs)
+        out = {"oracle_true_rel_residual": float(np.linalg.norm(r) / np.linalg.norm(b))}
+        if inner == w.WD_FP64:
+            x_fp64[dims] = xs
+        elif dims in x_fp64:
+            ref = x_fp64[dims]
+            out["rel_diff_vs_fp64_solution"] = float(np.linalg.norm(xs - ref) / np.linalg.norm(ref))
+        return out
 
     def run(dims, lat, inner, use_graph):
-        ghi, glo, bd, x, b = lat
+        ghi, glo, bd, x, b, _ = lat
         for g in {id(ghi): ghi, id(glo[inner]): glo[inner]}.values():
             tune(torch, w, g, 1, g.pack(b))
         ws = torch.empty(w.cg_workspace_bytes(dims, 1, inner), dtype=torch.uint8, device="cuda")
@@ -249,7 +280,7 @@ def bench_cg(torch, w, li, DeviceGauge, reps=3, cpu=True):
         dt = (time.perf_counter() - t0) / reps
         return {"status": rc, "solves_per_s": round(1.0 / dt, 2), "ms_per_solve": round(dt * 1e3, 3),
                 "iters": st[0]["iters"], "reliable_updates": st[0]["reliable_updates"],
-                "true_rel_residual": st[0]["true_rel_residual"]}
+                "true_rel_residual": st[0]["true_rel_residual"], **check(dims, lat, inner, use_graph)}
 
     dims = (24, 24, 24, 24)
     lat = setup(dims)
@@ -258,7 +289,6 @@ def bench_cg(torch, w, li, DeviceGauge, reps=3, cpu=True):
     if cpu:
         # the oracle's CG (FP64 numpy, one core) timed over 5 iterations and
         # extrapolated to the GPU FP64 solver's iteration count
-        import oracle
         U = li.near_unity_gauge(dims, li.seed_gauge(4), 0.3)
         b = li.gaussian_spinor(dims, li.seed_spinor(4))
         t0 = time.perf_counter()
@@ -520,8 +550,12 @@ def main(argv=None):
             if (p, c) == (args.prec, args.c12):
                 continue
             gv, sv, dv, msv, _, tv = measure(p, c, max(20, args.steps // 4), 5)
+            outv = gv.unpack(dv).reshape(-1, 4, 3)
+            errv = float(np.linalg.norm(outv[sites[:512]] - ref[:512]) / np.linalg.norm(ref[:512]))
+            tolv = {"fp64": 1e-13, "fp32": 1e-6, "fp16": 2e-3}[p]
             variants[f"{p}{'_c12' if c else ''}"] = {
                 "ms_per_apply": round(msv, 5), "tuning": tv,
+                "parity": {"rel_err": errv, "tol": tolv, "sites": 512, "ok": errv <= tolv},
                 "gflops": round(FLOPS_PER_SITE * V / (msv / 1e3) / 1e9, 1),
                 "pct_hbm_peak": round(100 * compulsory_bytes(p, c) * V / (msv / 1e3) / 1e9
                                       / HBM_PEAK_GBS, 2)}
