@@ -106,6 +106,37 @@ def copy_calibration(torch, nbytes=1 << 30, reps=5):
     return 2 * nbytes / t / 1e9
 
 
+def stream_triad(torch, nbytes=1 << 30, reps=10):
+    """STREAM triad a = b + s c on FP64 arrays of nbytes each (torch's own
+    elementwise kernel): the achievable-bandwidth ceiling of a plain stream.
+    Returns GB/s (two reads + one write)."""
+    n = nbytes // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.ones_like(a)
+    torch.add(b, c, alpha=3.0, out=a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(b, c, alpha=3.0, out=a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    return 3 * n * 8 / t / 1e9
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 TUNE = True  # set from --no-tune
 
 
@@ -226,7 +257,7 @@ def bench_multi(torch, w, li, DeviceGauge, prec="fp32", steps=50, warmup=5, inpu
             "tuning": tuned}
 
 
-def bench_cg(torch, w, li, DeviceGauge, reps=3, cpu=True):
+def bench_cg(torch, w, li, DeviceGauge, reps=5, cpu=True):
     """Solves of D^dag D x = b on 24^4, m = 0.05, near-unity links, to a true
     residual of 1e-10: plain FP64 CG against FP32 or FP16-storage inner
     iterations with FP64 reliable updates, eager and with chunks of iterations
@@ -561,6 +592,7 @@ def main(argv=None):
                                       / HBM_PEAK_GBS, 2)}
             del gv, sv, dv
     copy_gbs = copy_calibration(torch)
+    triad_gbs = stream_triad(torch)
     del Ud, psid
     multi = None
     if not args.no_multi:
@@ -599,7 +631,8 @@ def main(argv=None):
         cpu = {"value": round(FLOPS_PER_SITE * V / tc / 1e9, 4), "unit": "GFlop/s", "cores": 1,
                "kind": "oracle",
                "sample": f"one full FP64 application on the {'x'.join(map(str, dims))} lattice "
-                         f"({tc:.1f} s, numpy, single thread, {os.cpu_count()} host cores visible)"}
+                         f"({tc:.1f} s, numpy, single thread, {os.cpu_count()} host cores visible, "
+                         f"{cpu_model()})"}
 
     line = {
         "metric": METRIC,
@@ -626,6 +659,7 @@ def main(argv=None):
         "pack_ms": round(pack_ms, 4),
         "tuning": tuned,
         "torch_copy_gbs": round(copy_gbs, 1),
+        "stream_triad_gbs": round(triad_gbs, 1),
         "variants": variants,
         "latency_4x4x4x4": latency,
         "multi_rhs": multi,
