@@ -41,16 +41,18 @@ def compulsory_bytes(prec: str, c12: bool) -> int:
 
 # HBM traffic of the dslash kernel measured with rocprofv3 --pmc (FETCH_SIZE,
 # WRITE_SIZE), scaled by the same counters on a plain copy of known size; valid
-# only for the kernel sources it was measured on (hash below), else null.
+# only for the kernel sources it was measured on (hash below) and the launch
+# timed, else null.
 TRAFFIC = {
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated KiB per dispatch), measured for
-    # the kernel sources hashed below and the launch (tb, gw, group, rb) the bytes belong to
-    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "43289d3c489e5547", "launch": [32, 1, 32, 1],
-                                       "bytes_per_launch": 2257420312},   # 905,670.0 / 393,216.0
-    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "43289d3c489e5547", "launch": [16, 1, 64, 1],
-                                       "bytes_per_launch": 1125230017},   # 451,135.7 / 196,608.0
-    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "43289d3c489e5547", "launch": [4, 1, 256, 1],
-                                       "bytes_per_launch": 621374857},    # 250,163.8 / 106,496.0
+    # the kernel sources hashed below, per launch "tb,gw,group,rb" the bytes belong to
+    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "f9b0b126a66d26b5", "launches": {
+        "32,1,32,1": 2254796698,    # 904,389.1 / 393,216.0
+        "16,1,64,1": 2378550749}},  # 964,817.4 / 393,216.0
+    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "f9b0b126a66d26b5", "launches": {
+        "16,1,64,1": 1124094734}},  # 450,581.4 / 196,608.0
+    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "f9b0b126a66d26b5", "launches": {
+        "4,1,256,1": 622511081}},   # 250,718.6 / 106,496.0
 }
 KERNEL_SOURCES = ["paper_1901_07294_amd/csrc/dslash.hip", "paper_1901_07294_amd/csrc/stencil.h",
                   "paper_1901_07294_amd/csrc/fields.h", "paper_1901_07294_amd/csrc/cplx.h"]
@@ -613,9 +615,9 @@ def main(argv=None):
     key = f"{workload}_{args.prec}{'_c12' if args.c12 else ''}"
     traffic = None
     rec = TRAFFIC.get(key)
-    launch = [tuned[k] for k in ("tb", "gw", "group", "rb")] if tuned else None
-    if rec and rec["source_sha"] == kernel_source_hash() and rec["launch"] == launch:
-        traffic = rec["bytes_per_launch"]
+    launch = ",".join(str(tuned[k]) for k in ("tb", "gw", "group", "rb")) if tuned else None
+    if rec and rec["source_sha"] == kernel_source_hash() and launch in rec["launches"]:
+        traffic = rec["launches"][launch]
 
     serve = None
     if not args.no_serve:

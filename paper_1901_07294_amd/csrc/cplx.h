@@ -38,14 +38,25 @@ __device__ __forceinline__ cx<R> addi(cx<R> a, cx<R> b) { return {a.re - b.im, a
 template <typename R>
 __device__ __forceinline__ cx<R> subi(cx<R> a, cx<R> b) { return {a.re + b.im, a.im - b.re}; }
 
+// a*b rounded once. In FP32 it is spelled as a multiply-add with +0, which
+// gives the same value (an exact zero product comes out as +0), so that every
+// use of a link entry is a multiply-add operand: with binary16 links the
+// compiler then folds each conversion to FP32 into a mixed-precision
+// multiply-add instead of converting separately.
+template <typename R>
+__device__ __forceinline__ R prod(R a, R b) {
+  if constexpr (sizeof(R) == 4) return fmar(a, b, R(0));
+  else return a * b;
+}
+
 // a*b and conj(a)*b
 template <typename R>
 __device__ __forceinline__ cx<R> mul(cx<R> a, cx<R> b) {
-  return {fmar(a.re, b.re, -(a.im * b.im)), fmar(a.re, b.im, a.im * b.re)};
+  return {fmar(a.re, b.re, -prod(a.im, b.im)), fmar(a.re, b.im, prod(a.im, b.re))};
 }
 template <typename R>
 __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
-  return {fmar(a.re, b.re, a.im * b.im), fmar(a.re, b.im, -(a.im * b.re))};
+  return {fmar(a.re, b.re, prod(a.im, b.im)), fmar(a.re, b.im, -prod(a.im, b.re))};
 }
 // c + a*b and c + conj(a)*b
 template <typename R>

@@ -157,7 +157,9 @@ __device__ __forceinline__ long half_scale_index(long s) {
 
 // The product float(q) * scale is rounded on its own (contraction is off),
 // so a site reads the same FP32 values whether they come from here or from a
-// copy staged in LDS.
+// copy staged in LDS. It is written as a multiply-add with +0 (the same
+// value; an exact zero comes out as +0) so that the conversion from binary16
+// folds into one mixed-precision multiply-add.
 __device__ __forceinline__ void load_spinor(const h8* __restrict__ p, long /*V*/, int s,
                                             cx<float> (&v)[12]) {
   const float sc = reinterpret_cast<const float*>(p)[half_scale_index(s)];
@@ -166,7 +168,8 @@ __device__ __forceinline__ void load_spinor(const h8* __restrict__ p, long /*V*/
     const h8 t = p[half_unit(s, j)];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      v[4 * j + k] = {static_cast<float>(t[2 * k]) * sc, static_cast<float>(t[2 * k + 1]) * sc};
+      v[4 * j + k] = {fmar(static_cast<float>(t[2 * k]), sc, 0.0f),
+                      fmar(static_cast<float>(t[2 * k + 1]), sc, 0.0f)};
   }
 }
 
