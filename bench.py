@@ -422,17 +422,22 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
             time.sleep(0.0005)
         return done, time.time() - t0
 
-    def worst_residual(lat, done):
-        worst = 0.0
-        for rc, res, (i, m, x) in done.values():
+    def worst_residual(lat, done, limit=12):
+        """Largest true residual the oracle recomputes over a sample of at most
+        `limit` right-hand sides of the 8^4 and 16^4 requests (smallest first)."""
+        worst, checked = 0.0, 0
+        small = [v for v in done.values() if lat[v[2][0]]["U"] is not None]
+        small.sort(key=lambda v: li.volume(lat[v[2][0]]["dims"]))
+        for rc, res, (i, m, x) in small:
+            if checked >= limit:
+                break
             L = lat[i]
-            if L["U"] is None:
-                continue
             xs = L["packer"].unpack(x, nrhs=len(m))
             xs = xs if len(m) > 1 else xs[None]
-            for k in range(len(m)):
+            for k in range(min(len(m), limit - checked)):
                 r = L["b"][k] - oracle.normal_op(L["U"], m[k], xs[k])
                 worst = max(worst, float(np.linalg.norm(r) / np.linalg.norm(L["b"][k])))
+                checked += 1
         return worst
 
     def pct(v, q):
@@ -474,7 +479,7 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
             lv = out["levels"][-1]
             print(f"[bench] serving load {load}: p50 {lv['p50_ms']} ms, p99 {lv['p99_ms']} ms",
                   file=sys.stderr, flush=True)
-        out["max_true_rel_residual_small_lattices"] = worst
+        out["max_true_rel_residual_oracle_sample"] = worst  # 12 RHS of 8^4 / 16^4 requests per run
         out["arena_peak_gb"] = round(w.wd_server_info(srv)["arena_peak"] / 1e9, 2)
     finally:
         w.wd_server_destroy(srv)
