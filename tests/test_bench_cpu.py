@@ -1,0 +1,36 @@
+"""bench.py's command-line contract on the CPU: one GPU only, and the traffic
+table refers to the kernel sources it was measured on."""
+
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_defaults_and_tuning_option():
+    a = bench.parse([])
+    assert a.gpus == 1 and a.steps > 0 and a.warmup >= 0 and a.prec == "fp64" and a.tuning is None
+    assert bench.parse(["--tuning", "32,1,32,1"]).tuning == "32,1,32,1"
+
+
+def test_traffic_table_entries_name_launches_and_byte_counts():
+    for key, rec in bench.TRAFFIC.items():
+        assert key.startswith("wilson_dslash_")
+        assert len(rec["source_sha"]) == 16
+        for launch, nbytes in rec["launches"].items():
+            assert len(launch.split(",")) == 4 and nbytes > 0
+    # the FP64 entry exceeds the compulsory 960 B/site (reads are never below compulsory)
+    v = 32 * 32 * 32 * 64
+    for nbytes in bench.TRAFFIC["wilson_dslash_32x32x32x64_fp64"]["launches"].values():
+        assert nbytes >= 960 * v
