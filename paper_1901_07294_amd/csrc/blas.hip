@@ -12,6 +12,7 @@
 // depends only on the lattice, never on how many right-hand sides are in
 // flight or on timing: results are bitwise reproducible.
 #include "blas.h"
+#include "cg_site.h"
 #include "fields.h"
 
 namespace wd {
@@ -36,12 +37,6 @@ __device__ __forceinline__ double block_sum(double v) {
   if (threadIdx.x == 0)
     for (int i = 0; i < kThreads / 64; ++i) s += part[i];
   return s;
-}
-
-__device__ __forceinline__ double norm2(double2 a) { return fmar(a.x, a.x, a.y * a.y); }
-__device__ __forceinline__ double norm2(float4 a) {
-  const double x = a.x, y = a.y, z = a.z, w = a.w;
-  return fmar(x, x, fmar(y, y, fmar(z, z, w * w)));
 }
 
 // <p, A p> and alpha = <r, r> / <p, A p> from the partial sums of the
@@ -300,35 +295,6 @@ __global__ __launch_bounds__(kThreads) void zero_kernel(T* __restrict__ dst, lon
 
 // ------------------------------------------------------------ FP16 fields
 
-__device__ __forceinline__ double site_norm2(const cx<float> (&v)[12]) {
-  double s = 0.0;
-#pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    const double re = v[c].re, im = v[c].im;
-    s = fmar(re, re, fmar(im, im, s));
-  }
-  return s;
-}
-
-// Quantises and stores a site (cached stores: CG vectors are read again at
-// once); returns the squared norm of the values as stored.
-__device__ __forceinline__ double store_half_site(h8* __restrict__ p, long s, const cx<float> (&v)[12]) {
-  h8 q[3];
-  const float m = half_quantise(v, q);
-#pragma unroll
-  for (int j = 0; j < 3; ++j) p[half_unit(s, j)] = q[j];
-  reinterpret_cast<float*>(p)[half_scale_index(s)] = m;
-  double n = 0.0;
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const double d = static_cast<float>(q[j][k]) * m;
-      n = fmar(d, d, n);
-    }
-  return n;
-}
-
 #define WD_SITE_LOOP(i, V) \
   for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < (V); \
        i += static_cast<long>(gridDim.x) * kThreads)
@@ -355,27 +321,14 @@ __global__ __launch_bounds__(kThreads) void update_xr_half_kernel(
     long units, long nlo32, long V, RhsSet set, double* __restrict__ scal,
     const double* __restrict__ pap, int npap, double* __restrict__ partials) {
   const int k = set.idx[blockIdx.y];
-  const float a = static_cast<float>(alpha_from_partials(pap + k * npap, npap, scal + k * kScalars));
+  const double a = alpha_from_partials(pap + k * npap, npap, scal + k * kScalars);
   float4* xk = x + k * nlo32;
   h8* rk = r + k * units;
   double s = 0.0;
   WD_SITE_LOOP(i, V) {
-    cx<float> pv[12], rv[12], av[12];
-    load_spinor(p + k * units, V, static_cast<int>(i), pv);
-    load_spinor(rk, V, static_cast<int>(i), rv);
+    cx<float> av[12];
     load_spinor(ap + k * units, V, static_cast<int>(i), av);
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      float4 xe = xk[pidx(i, j, 6, V)];
-      xe.x = fmar(a, pv[2 * j].re, xe.x);
-      xe.y = fmar(a, pv[2 * j].im, xe.y);
-      xe.z = fmar(a, pv[2 * j + 1].re, xe.z);
-      xe.w = fmar(a, pv[2 * j + 1].im, xe.w);
-      xk[pidx(i, j, 6, V)] = xe;
-    }
-#pragma unroll
-    for (int c = 0; c < 12; ++c) rv[c] = {fmar(-a, av[c].re, rv[c].re), fmar(-a, av[c].im, rv[c].im)};
-    s += store_half_site(rk, i, rv);
+    s += cg_site_update(xk, rk, p + k * units, V, i, av, a);
   }
   s = block_sum(s);
   if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;

@@ -36,8 +36,10 @@ size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
 // Plain FP64 CG keeps r, p, t, Ap in FP64 (the true-residual recompute reuses
 // r and t); mixed CG adds FP64 r and t and the FP32 solution accumulator.
-CgLayout cg_layout(long V, int slots, int inner) {
+CgLayout cg_layout(const int32_t dims[4], int slots, int inner) {
   CgLayout w;
+  const long V = static_cast<long>(dims[0]) * dims[1] * dims[2] * dims[3];
+  w.nslices = cg_fuse_slices(dims, inner);
   const size_t hi = align256(static_cast<size_t>(packed_sites(V)) * slots * spinor_site_bytes(WD_FP64));
   const size_t lo = align256(static_cast<size_t>(packed_sites(V)) * slots * spinor_site_bytes(inner));
   const size_t acc = align256(static_cast<size_t>(packed_sites(V)) * slots * spinor_site_bytes(WD_FP32));
@@ -50,7 +52,10 @@ CgLayout cg_layout(long V, int slots, int inner) {
   w.r = o; o += lo;
   w.p = o; o += lo;
   w.t = o; o += lo;
-  w.ap = o; o += lo;
+  if (w.nslices == 0) {
+    w.ap = o;
+    o += lo;
+  }
   if (inner == WD_FP64) {
     w.r_hi = w.r;
     w.t_hi = w.t;
@@ -58,6 +63,7 @@ CgLayout cg_layout(long V, int slots, int inner) {
   w.partials = o; o += align256(static_cast<size_t>(slots) * kMaxPartials * sizeof(double));
   w.pap = o; o += align256(static_cast<size_t>(slots) * kMaxPartials * sizeof(double));
   w.scal = o; o += align256(static_cast<size_t>(slots) * kScalars * sizeof(double));
+  w.rr = o; o += align256(static_cast<size_t>(slots) * w.nslices * sizeof(double));
   w.bytes = o;
   return w;
 }
@@ -88,8 +94,9 @@ CgEngine::CgEngine(const wd_gauge* ghi, const wd_gauge* glo, int inner, int slot
   nlo_ = inner_ == WD_FP64 ? spinor_units<double>(V_)
                            : inner_ == WD_FP32 ? spinor_units<float>(V_) : spinor_units<_Float16>(V_);
   n32_ = spinor_units<float>(V_);
-  lay_ = cg_layout(V_, slots, inner_);
+  lay_ = cg_layout(ghi->dims, slots, inner_);
   partials_ = reinterpret_cast<double*>(at(ws_, lay_.partials));
+  rr_ = reinterpret_cast<double*>(at(ws_, lay_.rr));
   pap_ = reinterpret_cast<double*>(at(ws_, lay_.pap));
   scal_ = reinterpret_cast<double*>(at(ws_, lay_.scal));
 }
@@ -123,6 +130,32 @@ int CgEngine::iterate(const RhsSet& set) {
   for (int i = 0; i < set.n; ++i) m[i] = masses_[set.idx[i]];
   int rc = launch_status(launch_dslash_multi(glo_, m, set.n, set.idx, at(ws_, lay_.p),
                                              at(ws_, lay_.t), WD_FLAG_GAMMA5, st_), "cg: Q p");
+  if (lay_.nslices > 0) {
+    // <p, A p> = |Q p|^2 partial sums; then Q applied to Q p with the x, r
+    // update in its epilogue (A p is used at once, not stored), leaving the
+    // <r, r> partial sums of every tile slice; p update with beta
+    int npap = 0;
+    if (rc == WD_OK)
+      rc = launch_status(blas_norm2_partials(at(ws_, lay_.t), inner_, nlo_, V_, set, pap_, &npap, st_),
+                         "cg: pAp");
+    CgFuse f{};
+    f.x = inner_ == WD_FP64 ? x_ : at(ws_, lay_.x_lo);
+    f.xstride = inner_ == WD_FP64 ? nhi_ : n32_;
+    f.r = at(ws_, lay_.r);
+    f.p = at(ws_, lay_.p);
+    f.pap = pap_;
+    f.npap = npap;
+    f.rr = rr_;
+    f.nslices = lay_.nslices;
+    f.scal = scal_;
+    if (rc == WD_OK)
+      rc = launch_status(launch_dslash_cg(glo_, m, set.n, set.idx, at(ws_, lay_.t), f, st_),
+                         "cg: Q Q p with x, r");
+    if (rc == WD_OK)
+      rc = launch_status(blas_update_p(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, V_, set, rr_,
+                                       lay_.nslices, scal_, st_), "cg: p");
+    return rc;
+  }
   if (rc == WD_OK)
     rc = launch_status(launch_dslash_multi(glo_, m, set.n, set.idx, at(ws_, lay_.t),
                                            at(ws_, lay_.ap), WD_FLAG_GAMMA5, st_), "cg: Q Q p");
@@ -370,7 +403,7 @@ size_t cg_workspace_bytes(const int32_t dims[4], int32_t nrhs, int32_t inner) {
   long V = 0;
   if (check_dims(dims, &V) != WD_OK || nrhs < 1 || nrhs > kMaxRhs) return 0;
   if (inner != WD_FP64 && inner != WD_FP32 && inner != WD_FP16) return 0;
-  return cg_layout(V, nrhs, inner).bytes;
+  return cg_layout(dims, nrhs, inner).bytes;
 }
 
 int cg_solve_normal(const wd_gauge* g_hi, const wd_gauge* g_lo, const double* masses_host,
@@ -408,7 +441,7 @@ int cg_solve_normal(const wd_gauge* g_hi, const wd_gauge* g_lo, const double* ma
     const size_t vec = static_cast<size_t>(packed_sites(V)) * nrhs * spinor_site_bytes(WD_FP64);
     if ((rc = check_device_range(b_dev, vec, "b_dev")) != WD_OK) return rc;
     if ((rc = check_device_range(x_dev, vec, "x_dev")) != WD_OK) return rc;
-    const size_t need = cg_layout(V, nrhs, p.inner).bytes;
+    const size_t need = cg_layout(g_hi->dims, nrhs, p.inner).bytes;
     if (ws_bytes < need) return set_error(WD_ERR_INVALID_ARG, "ws_bytes %zu < %zu needed", ws_bytes, need);
     if ((rc = check_device_range(ws_dev, need, "ws_dev")) != WD_OK) return rc;
     if (overlaps(b_dev, vec, x_dev, vec) || overlaps(b_dev, vec, ws_dev, need) ||

@@ -9,12 +9,16 @@
 
 namespace wd {
 
-// Offsets (bytes) of a CG workspace for `slots` right-hand sides.
+// Offsets (bytes) of a CG workspace for `slots` right-hand sides. Where the
+// x, r update is fused into the second application of Q (nslices > 0), A p
+// is never stored and rr holds the <r,r> partial sums of its tile slices.
 struct CgLayout {
   size_t bytes = 0;
-  size_t r_hi = 0, t_hi = 0, x_lo = 0, r = 0, p = 0, t = 0, ap = 0, partials = 0, pap = 0, scal = 0;
+  size_t r_hi = 0, t_hi = 0, x_lo = 0, r = 0, p = 0, t = 0, ap = 0, partials = 0, pap = 0, scal = 0,
+         rr = 0;
+  int nslices = 0;
 };
-CgLayout cg_layout(long V, int slots, int inner);
+CgLayout cg_layout(const int32_t dims[4], int slots, int inner);
 
 size_t align256(size_t b);
 
@@ -63,6 +67,7 @@ class CgEngine {
   long V_ = 0, nhi_ = 0, nlo_ = 0, n32_ = 0;
   CgLayout lay_;
   double* partials_ = nullptr;
+  double* rr_ = nullptr;
   double* pap_ = nullptr;
   double* scal_ = nullptr;
   double masses_[kMaxRhs] = {};

@@ -1,0 +1,129 @@
+// One site's CG vector update x += alpha p, r -= alpha (A p), for the three
+// storage precisions, shared by the CG vector kernels and by the dslash
+// launch that fuses the update into its epilogue. Returns the site's
+// contribution to <r, r> (of the values as stored).
+#pragma once
+
+#include "fields.h"
+
+namespace wd {
+
+__device__ __forceinline__ double norm2(double2 a) { return fmar(a.x, a.x, a.y * a.y); }
+__device__ __forceinline__ double norm2(float4 a) {
+  const double x = a.x, y = a.y, z = a.z, w = a.w;
+  return fmar(x, x, fmar(y, y, fmar(z, z, w * w)));
+}
+
+__device__ __forceinline__ double site_norm2(const cx<float> (&v)[12]) {
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const double re = v[c].re, im = v[c].im;
+    s = fmar(re, re, fmar(im, im, s));
+  }
+  return s;
+}
+
+// Quantises and stores a site (cached stores: CG vectors are read again at
+// once); returns the squared norm of the values as stored.
+__device__ __forceinline__ double store_half_site(h8* __restrict__ p, long s, const cx<float> (&v)[12]) {
+  h8 q[3];
+  const float m = half_quantise(v, q);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) p[half_unit(s, j)] = q[j];
+  reinterpret_cast<float*>(p)[half_scale_index(s)] = m;
+  double n = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double d = static_cast<float>(q[j][k]) * m;
+      n = fmar(d, d, n);
+    }
+  return n;
+}
+
+// FP64 vectors: x is the FP64 solution; ap holds A p at the site.
+__device__ __forceinline__ double cg_site_update(double2* __restrict__ x, double2* __restrict__ r,
+                                                 const double2* __restrict__ p, long V, long s,
+                                                 const cx<double> (&ap)[12], double alpha) {
+  double n = 0.0;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const long e = pidx(s, c, 12, V);
+    double2 xe = x[e];
+    double2 re = r[e];
+    const double2 pe = p[e];
+    xe.x = fmar(alpha, pe.x, xe.x);
+    xe.y = fmar(alpha, pe.y, xe.y);
+    re.x = fmar(-alpha, ap[c].re, re.x);
+    re.y = fmar(-alpha, ap[c].im, re.y);
+    x[e] = xe;
+    r[e] = re;
+    n += norm2(re);
+  }
+  return n;
+}
+
+// FP32 vectors: x is the FP32 accumulator x_lo (same layout as r and p).
+__device__ __forceinline__ double cg_site_update(float4* __restrict__ x, float4* __restrict__ r,
+                                                 const float4* __restrict__ p, long V, long s,
+                                                 const cx<float> (&ap)[12], double alpha) {
+  const float a = static_cast<float>(alpha);
+  double n = 0.0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const long e = pidx(s, j, 6, V);
+    float4 xe = x[e];
+    float4 re = r[e];
+    const float4 pe = p[e];
+    xe.x = fmar(a, pe.x, xe.x);
+    xe.y = fmar(a, pe.y, xe.y);
+    xe.z = fmar(a, pe.z, xe.z);
+    xe.w = fmar(a, pe.w, xe.w);
+    re.x = fmar(-a, ap[2 * j].re, re.x);
+    re.y = fmar(-a, ap[2 * j].im, re.y);
+    re.z = fmar(-a, ap[2 * j + 1].re, re.z);
+    re.w = fmar(-a, ap[2 * j + 1].im, re.w);
+    x[e] = xe;
+    r[e] = re;
+    n += norm2(re);
+  }
+  return n;
+}
+
+// FP16-storage vectors: x is the FP32 accumulator x_lo (FP32 layout); r is
+// requantised per site.
+__device__ __forceinline__ double cg_site_update(float4* __restrict__ x, h8* __restrict__ r,
+                                                 const h8* __restrict__ p, long V, long s,
+                                                 const cx<float> (&ap)[12], double alpha) {
+  const float a = static_cast<float>(alpha);
+  cx<float> pv[12], rv[12];
+  load_spinor(p, V, static_cast<int>(s), pv);
+  load_spinor(r, V, static_cast<int>(s), rv);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const long e = pidx(s, j, 6, V);
+    float4 xe = x[e];
+    xe.x = fmar(a, pv[2 * j].re, xe.x);
+    xe.y = fmar(a, pv[2 * j].im, xe.y);
+    xe.z = fmar(a, pv[2 * j + 1].re, xe.z);
+    xe.w = fmar(a, pv[2 * j + 1].im, xe.w);
+    x[e] = xe;
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) rv[c] = {fmar(-a, ap[c].re, rv[c].re), fmar(-a, ap[c].im, rv[c].im)};
+  return store_half_site(r, s, rv);
+}
+
+// alpha = <r, r> / <p, A p> and its failure flag from <p, A p> = t.
+__device__ __forceinline__ double cg_alpha(double t, double rr, bool* flag) {
+  *flag = !isfinite(t);
+  if (!(t > 0.0)) {
+    if (rr > 0.0) *flag = true;
+    return 0.0;
+  }
+  return rr / t;
+}
+
+}  // namespace wd

@@ -10,7 +10,10 @@
 // bytes per site in FP64), so there is no matrix-core work here: every lane
 // streams its site's links and spinor planes, coalesced across the wave.
 #include <atomic>
+#include <type_traits>
 
+#include "blas.h"
+#include "cg_site.h"
 #include "stencil.h"
 #include "wd_internal.h"
 
@@ -185,15 +188,29 @@ __device__ __forceinline__ void outer_hops(const SV* const (&in)[RB], const LV* 
   if (y_bwd_out) hop_rb<1, +1, C12>(in, links, V, st + dym, st + dym, acc);
 }
 
+// Sum over the 64 lanes of a wave in a fixed order (every lane gets it).
+__device__ __forceinline__ double wave_total(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Doubles of LDS per lane group and right-hand side that the fused CG update
+// uses after the spinor slices: per-wave <r,r> sums of two steps (tiles of at
+// most 4 waves) and alpha.
+constexpr int kCgLds = 2 * 4 + 1;
+
 // MAXT: launch bound. A workgroup holds p.gw groups of n = X * ny lanes of
 // one tile; each lane carries RB right-hand sides (links loaded once for
 // all), each with its own two LDS slices. The LDS slices hold spinors in the
 // arithmetic precision (FP32 for FP16 storage).
-template <typename T, bool C12, int MAXT, int RB>
+// With CG the output is not stored: the epilogue applies the CG update of
+// cgf to the field slots instead (n must be a multiple of 64).
+template <typename T, bool C12, int MAXT, int RB, bool CG>
 __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
     const typename Packed<T>::S* __restrict__ in, typename Packed<T>::S* __restrict__ out,
     const typename Packed<T>::L* __restrict__ links, Geo geo, Diag<typename Packed<T>::R> diags,
-    long stride, int gamma5, MarchParams p) {
+    long stride, int gamma5, MarchParams p, CgFuse cgf) {
   using R = typename Packed<T>::R;
   using SV = typename Packed<R>::S;
   using GS = typename Packed<T>::S;
@@ -252,6 +269,38 @@ __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
   for (int r = 0; r < RB; ++r)
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[r][c] = {R(0), R(0)};
+
+  // fused CG update: per lane group and right-hand side, kCgLds doubles after
+  // all spinor slices; alpha from the <p,Ap> partial sums, reduced by the
+  // group's first wave in a fixed order (the same in every workgroup), and
+  // recorded in the scalars by the workgroup of the field's first tile
+  using XV = typename std::conditional<sizeof(R) == 8, double2, float4>::type;
+  double* cgs = reinterpret_cast<double*>(reinterpret_cast<SV*>(smem) + p.gw * 2 * RB * kPlanes * n) +
+                slot * RB * kCgLds;
+  if constexpr (CG) {
+    if (tid < 64) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int k = diags.idx[rhs0 + r];
+        const double* pp = cgf.pap + static_cast<long>(k) * cgf.npap;
+        double t = 0.0;
+        for (int i = tid; i < cgf.npap; i += 64) t += pp[i];
+        t = wave_total(t);
+        if (tid == 0) {
+          double* sc = cgf.scal + static_cast<long>(k) * kScalars;
+          bool flag = false;
+          const double a = cg_alpha(t, sc[kRr], &flag);
+          cgs[r * kCgLds + 8] = a;
+          if (b == 0) {  // the field's first tile: one workgroup per field
+            sc[kPap] = t;
+            sc[kAlpha] = a;
+            sc[kRrPrev] = sc[kRr];
+            if (flag) sc[kFlag] = 1.0;
+          }
+        }
+      }
+    }
+  }
 
   // prologue: the carried hops of t0 (in the loop's order: outer hops, then
   // the backward t hop, so every site rounds alike) and the first slice in LDS
@@ -317,7 +366,17 @@ __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
       lds_load_spinor(cur[r], n, tid, psi);
       cx<R> o[12];
       epilogue(psi, acc[r], diag[r], gamma5, o);
-      store_spinor(outr[r], V, st, o);
+      if constexpr (CG) {
+        const long k = diags.idx[rhs0 + r];
+        double v = cg_site_update(static_cast<XV*>(cgf.x) + k * cgf.xstride,
+                                  const_cast<GS*>(reinterpret_cast<const GS*>(cgf.r)) + k * stride,
+                                  reinterpret_cast<const GS*>(cgf.p) + k * stride, V, st, o,
+                                  cgs[r * kCgLds + 8]);
+        v = wave_total(v);
+        if ((tid & 63) == 0) cgs[r * kCgLds + 4 * ((t - t0) & 1) + (tid >> 6)] = v;
+      } else {
+        store_spinor(outr[r], V, st, o);
+      }
       if (more) {
         cx<R> h[6], g[6];
         project<3, +1>(psi, h);
@@ -330,6 +389,19 @@ __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[r][c] = nacc[r][c];
     __syncthreads();
+    if constexpr (CG) {
+      // <r,r> of this tile slice: its waves in order (the next write to these
+      // words is two steps on, behind the next barrier)
+      if (tid == 0) {
+        const long ts = (static_cast<long>(t) * geo.Z + z) * p.ytiles + yt;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          double sum = 0.0;
+          for (int w = 0; w < n / 64; ++w) sum += cgs[r * kCgLds + 4 * ((t - t0) & 1) + w];
+          cgf.rr[static_cast<long>(diags.idx[rhs0 + r]) * cgf.nslices + ts] = sum;
+        }
+      }
+    }
   }
 }
 
@@ -400,45 +472,48 @@ MarchParams march_params(const Geo& geo, size_t real_bytes, int nrhs) {
   return p;
 }
 
-template <typename T, bool C12, int MAXT, int RB>
+template <typename T, bool C12, int MAXT, int RB, bool CG>
 hipError_t launch_march_t(const void* in, void* out, const void* links, const Geo& geo,
                           const Diag<typename Packed<T>::R>& diag, long stride, int g5,
-                          const MarchParams& p, hipStream_t st) {
+                          const MarchParams& p, const CgFuse& f, hipStream_t st) {
   using SV = typename Packed<T>::S;
   using LV = typename Packed<T>::L;
   using R = typename Packed<T>::R;
   const int n = geo.X * p.ny;
-  const size_t lds = static_cast<size_t>(p.gw) * RB * march_lds_bytes(n, sizeof(R));
+  size_t lds = static_cast<size_t>(p.gw) * RB * march_lds_bytes(n, sizeof(R));
+  if (CG) lds += static_cast<size_t>(p.gw) * RB * kCgLds * sizeof(double);
+  if (lds > kLdsBytes) return hipErrorInvalidValue;
   // raise the kernel's dynamic LDS limit once to the whole LDS of a CU
   static std::atomic<int> attr_set{0};
   if (!attr_set.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&dslash_march_kernel<T, C12, MAXT, RB>),
+        reinterpret_cast<const void*>(&dslash_march_kernel<T, C12, MAXT, RB, CG>),
         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
     if (e != hipSuccess) return e;
     attr_set.store(1, std::memory_order_release);
   }
   const unsigned nb = static_cast<unsigned>((p.nrhs / (p.gw * RB)) * p.ytiles * geo.Z *
                                             ((geo.T + p.tb - 1) / p.tb));
-  dslash_march_kernel<T, C12, MAXT, RB><<<nb, p.gw * n, lds, st>>>(
+  dslash_march_kernel<T, C12, MAXT, RB, CG><<<nb, p.gw * n, lds, st>>>(
       static_cast<const SV*>(in), static_cast<SV*>(out), static_cast<const LV*>(links), geo, diag,
-      stride, g5, p);
+      stride, g5, p, f);
   return hipGetLastError();
 }
 
-template <typename T, bool C12>
+template <typename T, bool C12, bool CG>
 hipError_t launch_march(const void* in, void* out, const void* links, const Geo& geo,
                         const Diag<typename Packed<T>::R>& diag, long stride, int g5,
-                        const MarchParams& p, hipStream_t st) {
+                        const MarchParams& p, const CgFuse& f, hipStream_t st) {
   if constexpr (sizeof(typename Packed<T>::R) == 4) {
     if (p.rb == 2)  // two right-hand sides per lane: one lane group per workgroup
-      return launch_march_t<T, C12, kMarchMaxThreads, 2>(in, out, links, geo, diag, stride, g5, p,
-                                                         st);
+      return launch_march_t<T, C12, kMarchMaxThreads, 2, CG>(in, out, links, geo, diag, stride, g5, p,
+                                                             f, st);
     if (p.gw > 1)
-      return launch_march_t<T, C12, kMarchMultiThreads, 1>(in, out, links, geo, diag, stride, g5, p,
-                                                           st);
+      return launch_march_t<T, C12, kMarchMultiThreads, 1, CG>(in, out, links, geo, diag, stride, g5,
+                                                               p, f, st);
   }
-  return launch_march_t<T, C12, kMarchMaxThreads, 1>(in, out, links, geo, diag, stride, g5, p, st);
+  return launch_march_t<T, C12, kMarchMaxThreads, 1, CG>(in, out, links, geo, diag, stride, g5, p, f,
+                                                         st);
 }
 
 template <typename T, bool C12>
@@ -464,10 +539,11 @@ MarchParams with_tuning(MarchParams p, const MarchTuning& t) {
   return p;
 }
 
+// cg: the fused CG update (the march kernel only; nullptr for a plain apply).
 template <typename T, bool C12>
 hipError_t launch_typed(const wd_gauge* g, const void* in, void* out, const Geo& geo,
                         const double* masses, int nrhs, const int* fields, int g5,
-                        const MarchTuning* force, hipStream_t st) {
+                        const MarchTuning* force, const CgFuse* cg, hipStream_t st) {
   using R = typename Packed<T>::R;
   Diag<R> diag{};
   for (int k = 0; k < nrhs; ++k) {
@@ -480,29 +556,40 @@ hipError_t launch_typed(const wd_gauge* g, const void* in, void* out, const Geo&
     MarchTuning t;
     if (force != nullptr) p = with_tuning(p, *force);
     else if (tuned_lookup(g->dims, g->prec, g->c12, nrhs, &t)) p = with_tuning(p, t);
-    return launch_march<T, C12>(in, out, g->links, geo, diag, stride, g5, p, st);
+    if (cg != nullptr) {
+      if constexpr (sizeof(R) == 4) {
+        if ((geo.X * p.ny) % 64 != 0) return hipErrorInvalidValue;
+        return launch_march<T, C12, true>(in, nullptr, g->links, geo, diag, stride, g5, p, *cg, st);
+      } else {
+        return hipErrorInvalidValue;
+      }
+    }
+    return launch_march<T, C12, false>(in, out, g->links, geo, diag, stride, g5, p, CgFuse{}, st);
   }
+  if (cg != nullptr) return hipErrorInvalidValue;
   return launch_site<T, C12>(in, out, g->links, geo, diag, nrhs, stride, g5, st);
 }
 
 template <typename T>
 hipError_t launch_prec(const wd_gauge* g, const void* in, void* out, const Geo& geo,
                        const double* masses, int nrhs, const int* fields, int g5,
-                       const MarchTuning* force, hipStream_t st) {
-  return g->c12 ? launch_typed<T, true>(g, in, out, geo, masses, nrhs, fields, g5, force, st)
-                : launch_typed<T, false>(g, in, out, geo, masses, nrhs, fields, g5, force, st);
+                       const MarchTuning* force, const CgFuse* cg, hipStream_t st) {
+  return g->c12 ? launch_typed<T, true>(g, in, out, geo, masses, nrhs, fields, g5, force, cg, st)
+                : launch_typed<T, false>(g, in, out, geo, masses, nrhs, fields, g5, force, cg, st);
 }
 
 hipError_t launch_any(const wd_gauge* g, const double* masses, int nrhs, const int* fields,
-                      const void* in, void* out, int flags, const MarchTuning* force, hipStream_t st) {
+                      const void* in, void* out, int flags, const MarchTuning* force,
+                      const CgFuse* cg, hipStream_t st) {
   if (nrhs < 1) return hipSuccess;
   if (nrhs > kMaxMultiRhs) return hipErrorInvalidValue;
   const Geo geo = make_geo(g->dims);
   const int g5 = (flags & WD_FLAG_GAMMA5) ? 1 : 0;
   switch (g->prec) {
-    case WD_FP64: return launch_prec<double>(g, in, out, geo, masses, nrhs, fields, g5, force, st);
-    case WD_FP32: return launch_prec<float>(g, in, out, geo, masses, nrhs, fields, g5, force, st);
-    case WD_FP16: return launch_prec<_Float16>(g, in, out, geo, masses, nrhs, fields, g5, force, st);
+    case WD_FP64: return launch_prec<double>(g, in, out, geo, masses, nrhs, fields, g5, force, cg, st);
+    case WD_FP32: return launch_prec<float>(g, in, out, geo, masses, nrhs, fields, g5, force, cg, st);
+    case WD_FP16:
+      return launch_prec<_Float16>(g, in, out, geo, masses, nrhs, fields, g5, force, cg, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -513,7 +600,24 @@ size_t real_bytes_of(int prec) { return prec == WD_FP64 ? 8 : 4; }
 
 hipError_t launch_dslash_multi(const wd_gauge* g, const double* masses, int nrhs, const int* fields,
                                const void* in, void* out, int flags, hipStream_t st) {
-  return launch_any(g, masses, nrhs, fields, in, out, flags, nullptr, st);
+  return launch_any(g, masses, nrhs, fields, in, out, flags, nullptr, nullptr, st);
+}
+
+// FP32 arithmetic only: the FP64 kernel holds one wave per SIMD, and the x, r
+// update in its epilogue cost more than the separate update kernel it saves
+// (24^4 FP64 CG 46.5 -> 47.9 ms per solve).
+int cg_fuse_slices(const int32_t dims[4], int prec) {
+  if (WD_DSLASH_KERNEL != 0 || prec == WD_FP64) return 0;
+  const Geo geo = make_geo(dims);
+  const MarchParams p = march_params(geo, real_bytes_of(prec), 1);
+  if (p.ny == 0 || (geo.X * p.ny) % 64 != 0) return 0;
+  const long n = static_cast<long>(geo.T) * geo.Z * p.ytiles;
+  return n <= 0x7fffffffL ? static_cast<int>(n) : 0;
+}
+
+hipError_t launch_dslash_cg(const wd_gauge* g, const double* masses, int nrhs, const int* fields,
+                            const void* in, const CgFuse& f, hipStream_t st) {
+  return launch_any(g, masses, nrhs, fields, in, nullptr, WD_FLAG_GAMMA5, nullptr, &f, st);
 }
 
 hipError_t launch_dslash(const wd_gauge* g, double mass, const void* in, void* out, int flags,
@@ -523,7 +627,7 @@ hipError_t launch_dslash(const wd_gauge* g, double mass, const void* in, void* o
 
 hipError_t launch_dslash_tuned(const wd_gauge* g, const double* masses, int nrhs, const void* in,
                                void* out, int flags, const MarchTuning& t, hipStream_t st) {
-  return launch_any(g, masses, nrhs, nullptr, in, out, flags, &t, st);
+  return launch_any(g, masses, nrhs, nullptr, in, out, flags, &t, nullptr, st);
 }
 
 bool march_default(const int32_t dims[4], int prec, int nrhs, MarchTuning* t) {

@@ -139,8 +139,8 @@ size_t inner_gauge_bytes(const int32_t dims[4], int inner) {
   return inner == WD_FP64 ? 0 : align256(wd_gauge_bytes(dims, inner, 0));
 }
 
-size_t group_bytes(long V, int S, int inner) {
-  return 2 * vec_bytes(V, S) + cg_layout(V, S, inner).bytes;
+size_t group_bytes(const int32_t dims[4], long V, int S, int inner) {
+  return 2 * vec_bytes(V, S) + cg_layout(dims, S, inner).bytes;
 }
 
 RhsSet set_of(const std::vector<int>& ks) {
@@ -176,10 +176,10 @@ Group* wd_server::make_group(GaugeEntry* ge, int need) {
   char* mem;
   {
     std::lock_guard<std::mutex> lk(mu);
-    mem = arena.alloc(group_bytes(ge->V, S, cfg.inner));
+    mem = arena.alloc(group_bytes(ge->dims, ge->V, S, cfg.inner));
     if (mem == nullptr && need < S) {
       S = need;
-      mem = arena.alloc(group_bytes(ge->V, S, cfg.inner));
+      mem = arena.alloc(group_bytes(ge->dims, ge->V, S, cfg.inner));
     }
   }
   if (mem == nullptr) return nullptr;
@@ -577,7 +577,7 @@ int cg_submit(wd_server* s, const wd_request* req, uint64_t* ticket) {
         if (!g->removing)
           gauges += align256(wd_gauge_bytes(g->dims, WD_FP64, 0)) + inner_gauge_bytes(g->dims, s->cfg.inner);
       lk.unlock();
-      if (group_bytes(ge->V, req->nrhs, s->cfg.inner) + gauges > s->cfg.arena_bytes)
+      if (group_bytes(ge->dims, ge->V, req->nrhs, s->cfg.inner) + gauges > s->cfg.arena_bytes)
         return set_error(WD_ERR_NOMEM, "a solve group of this lattice cannot fit beside the gauge fields");
     }
     auto rq = std::make_unique<Request>();

@@ -101,4 +101,29 @@ hipError_t launch_dslash_tuned(const wd_gauge* g, const double* masses, int nrhs
 // The autotuner's choice registered for (dims, prec, c12, nrhs), if any.
 bool tuned_lookup(const int32_t dims[4], int prec, int c12, int nrhs, MarchTuning* t);
 
+// The CG vector update fused into the second application of Q in an
+// iteration: the dslash epilogue uses Q t = A p at once for x += alpha p and
+// r -= alpha A p (alpha = <r,r> / <p,Ap> reduced from pap) instead of storing
+// it, and leaves the <r,r> partial sums of each tile slice (a tile's x rows
+// at one z and t, so the grouping is fixed by the lattice, not the launch).
+struct CgFuse {
+  void* x;            // FP64 solution (FP64 vectors) or FP32 accumulator x_lo
+  void* r;            // residual, inner precision
+  const void* p;      // search direction, inner precision
+  const double* pap;  // <p, A p> partial sums, npap per field slot
+  int npap;
+  double* rr;         // out: <r, r> per tile slice, nslices per field slot
+  int nslices;
+  double* scal;       // per field slot scalars (kScalars doubles)
+  long xstride;       // 16-byte elements of x per field slot
+};
+// Tile slices of the fused update on a lattice in an inner precision, or 0
+// where it does not apply (FP64, the one-site-per-lane kernel, or tiles that
+// are not whole waves).
+int cg_fuse_slices(const int32_t dims[4], int prec);
+// Q = gamma5 D(masses[i]) on field fields[i] of `in`, fused with the CG
+// update above for the same field slots (cg_fuse_slices must be > 0).
+hipError_t launch_dslash_cg(const wd_gauge* g, const double* masses, int nrhs, const int* fields,
+                            const void* in, const CgFuse& f, hipStream_t s);
+
 }  // namespace wd
