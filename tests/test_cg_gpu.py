@@ -209,3 +209,21 @@ def test_cg_argument_errors():
     assert code(x=b) == w.WD_ERR_INVALID_ARG
     assert code(masses=[float("inf")]) == w.WD_ERR_INVALID_ARG
     assert w.cg_workspace_bytes(dims, 0, w.WD_FP64) == 0
+
+
+@pytest.mark.parametrize("inner", ["fp32", "fp16"])
+def test_cg_mixed_on_tiles_that_are_not_whole_waves(inner):
+    """On a lattice whose t-marching tiles are not whole waves (12 x 6 = 72
+    sites) the x, r update runs as its own kernel instead of in the dslash
+    epilogue: same bar (oracle true residual, batch equals alone)."""
+    dims = (12, 6, 4, 4)
+    U = li.near_unity_gauge(dims, 91, 0.3)
+    bs = li.gaussian_spinors(dims, [92, 93])
+    masses = [0.05, 0.3]
+    rc, xs, stats, _ = solve(U, masses, bs, INNER[inner])
+    assert rc == w.WD_OK, stats
+    for k in range(2):
+        assert true_rel_residual(U, masses[k], bs[k], xs[k]) <= 1e-10
+        rc1, x1, _, _ = solve(U, [masses[k]], bs[k][None], INNER[inner])
+        assert rc1 == w.WD_OK
+        assert np.array_equal(x1[0], xs[k])
