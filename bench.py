@@ -46,13 +46,13 @@ def compulsory_bytes(prec: str, c12: bool) -> int:
 TRAFFIC = {
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated KiB per dispatch), measured for
     # the kernel sources hashed below, per launch "tb,gw,group,rb" the bytes belong to
-    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "f9b0b126a66d26b5", "launches": {
-        "32,1,32,1": 2254796698,    # 904,389.1 / 393,216.0
-        "16,1,64,1": 2378550749}},  # 964,817.4 / 393,216.0
-    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "f9b0b126a66d26b5", "launches": {
-        "16,1,64,1": 1124094734}},  # 450,581.4 / 196,608.0
-    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "f9b0b126a66d26b5", "launches": {
-        "4,1,256,1": 622511081}},   # 250,718.6 / 106,496.0
+    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "469a2c5eb232ad70", "launches": {
+        "32,1,32,1": 2254197747,    # 904,096.5 / 393,216.0
+        "16,1,64,1": 2371878913}},  # 961,559.4 / 393,216.0
+    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "469a2c5eb232ad70", "launches": {
+        "16,1,64,1": 1122585752}},  # 449,844.5 / 196,608.0
+    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "469a2c5eb232ad70", "launches": {
+        "4,1,256,1": 621534781}},   # 250,241.9 / 106,496.0
 }
 KERNEL_SOURCES = ["paper_1901_07294_amd/csrc/dslash.hip", "paper_1901_07294_amd/csrc/stencil.h",
                   "paper_1901_07294_amd/csrc/fields.h", "paper_1901_07294_amd/csrc/cplx.h"]
