@@ -79,7 +79,15 @@ __device__ __forceinline__ double beta_from_partials(const double* __restrict__ 
                                                      double* sc) {
   __shared__ double s_beta;
   double s = 0.0;
-  for (int i = threadIdx.x; i < np; i += kThreads) s += pp[i];
+  int i = threadIdx.x;
+  for (; i + 3 * kThreads < np; i += 4 * kThreads) {  // four loads in flight, added in order
+    const double a0 = pp[i], a1 = pp[i + kThreads], a2 = pp[i + 2 * kThreads], a3 = pp[i + 3 * kThreads];
+    s += a0;
+    s += a1;
+    s += a2;
+    s += a3;
+  }
+  for (; i < np; i += kThreads) s += pp[i];
   s = block_sum(s);
   if (threadIdx.x == 0) {
     const double old = sc[kRrPrev];

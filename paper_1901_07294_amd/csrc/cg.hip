@@ -64,6 +64,7 @@ CgLayout cg_layout(const int32_t dims[4], int slots, int inner) {
   w.pap = o; o += align256(static_cast<size_t>(slots) * kMaxPartials * sizeof(double));
   w.scal = o; o += align256(static_cast<size_t>(slots) * kScalars * sizeof(double));
   w.rr = o; o += align256(static_cast<size_t>(slots) * w.nslices * sizeof(double));
+  w.paps = o; o += align256(static_cast<size_t>(slots) * w.nslices * sizeof(double));
   w.bytes = o;
   return w;
 }
@@ -97,6 +98,7 @@ CgEngine::CgEngine(const wd_gauge* ghi, const wd_gauge* glo, int inner, int slot
   lay_ = cg_layout(ghi->dims, slots, inner_);
   partials_ = reinterpret_cast<double*>(at(ws_, lay_.partials));
   rr_ = reinterpret_cast<double*>(at(ws_, lay_.rr));
+  paps_ = reinterpret_cast<double*>(at(ws_, lay_.paps));
   pap_ = reinterpret_cast<double*>(at(ws_, lay_.pap));
   scal_ = reinterpret_cast<double*>(at(ws_, lay_.scal));
 }
@@ -128,34 +130,35 @@ int CgEngine::start(const RhsSet& set, bool x0_given) {
 int CgEngine::iterate(const RhsSet& set) {
   double m[kMaxRhs];
   for (int i = 0; i < set.n; ++i) m[i] = masses_[set.idx[i]];
-  int rc = launch_status(launch_dslash_multi(glo_, m, set.n, set.idx, at(ws_, lay_.p),
-                                             at(ws_, lay_.t), WD_FLAG_GAMMA5, st_), "cg: Q p");
   if (lay_.nslices > 0) {
-    // <p, A p> = |Q p|^2 partial sums; then Q applied to Q p with the x, r
-    // update in its epilogue (A p is used at once, not stored), leaving the
-    // <r, r> partial sums of every tile slice; p update with beta
-    int npap = 0;
-    if (rc == WD_OK)
-      rc = launch_status(blas_norm2_partials(at(ws_, lay_.t), inner_, nlo_, V_, set, pap_, &npap, st_),
-                         "cg: pAp");
+    // t = Q p, with <p, A p> = |t|^2 summed per tile slice in the same launch;
+    // then Q t = A p used at once for x += alpha p, r -= alpha A p, with
+    // <r, r> per tile slice (A p is never stored); then p = r + beta p
     CgFuse f{};
+    f.mode = kCgNorm;
+    f.rr = paps_;
+    f.nslices = lay_.nslices;
+    int rc = launch_status(launch_dslash_cg(glo_, m, set.n, set.idx, at(ws_, lay_.p), at(ws_, lay_.t), f,
+                                            st_), "cg: Q p with |Q p|^2");
+    f.mode = kCgUpdate;
     f.x = inner_ == WD_FP64 ? x_ : at(ws_, lay_.x_lo);
     f.xstride = inner_ == WD_FP64 ? nhi_ : n32_;
     f.r = at(ws_, lay_.r);
     f.p = at(ws_, lay_.p);
-    f.pap = pap_;
-    f.npap = npap;
+    f.pap = paps_;
+    f.npap = lay_.nslices;
     f.rr = rr_;
-    f.nslices = lay_.nslices;
     f.scal = scal_;
     if (rc == WD_OK)
-      rc = launch_status(launch_dslash_cg(glo_, m, set.n, set.idx, at(ws_, lay_.t), f, st_),
+      rc = launch_status(launch_dslash_cg(glo_, m, set.n, set.idx, at(ws_, lay_.t), nullptr, f, st_),
                          "cg: Q Q p with x, r");
     if (rc == WD_OK)
       rc = launch_status(blas_update_p(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, V_, set, rr_,
                                        lay_.nslices, scal_, st_), "cg: p");
     return rc;
   }
+  int rc = launch_status(launch_dslash_multi(glo_, m, set.n, set.idx, at(ws_, lay_.p),
+                                             at(ws_, lay_.t), WD_FLAG_GAMMA5, st_), "cg: Q p");
   if (rc == WD_OK)
     rc = launch_status(launch_dslash_multi(glo_, m, set.n, set.idx, at(ws_, lay_.t),
                                            at(ws_, lay_.ap), WD_FLAG_GAMMA5, st_), "cg: Q Q p");

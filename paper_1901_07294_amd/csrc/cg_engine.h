@@ -10,12 +10,13 @@
 namespace wd {
 
 // Offsets (bytes) of a CG workspace for `slots` right-hand sides. Where the
-// x, r update is fused into the second application of Q (nslices > 0), A p
-// is never stored and rr holds the <r,r> partial sums of its tile slices.
+// iteration's vector work is fused into its applications of Q (nslices > 0),
+// A p is never stored, and paps and rr hold the |Q p|^2 and <r,r> partial
+// sums of the tile slices.
 struct CgLayout {
   size_t bytes = 0;
   size_t r_hi = 0, t_hi = 0, x_lo = 0, r = 0, p = 0, t = 0, ap = 0, partials = 0, pap = 0, scal = 0,
-         rr = 0;
+         rr = 0, paps = 0;
   int nslices = 0;
 };
 CgLayout cg_layout(const int32_t dims[4], int slots, int inner);
@@ -68,6 +69,7 @@ class CgEngine {
   CgLayout lay_;
   double* partials_ = nullptr;
   double* rr_ = nullptr;
+  double* paps_ = nullptr;
   double* pap_ = nullptr;
   double* scal_ = nullptr;
   double masses_[kMaxRhs] = {};

@@ -1,7 +1,9 @@
 // One site's CG vector update x += alpha p, r -= alpha (A p), for the three
 // storage precisions, shared by the CG vector kernels and by the dslash
-// launch that fuses the update into its epilogue. Returns the site's
-// contribution to <r, r> (of the values as stored).
+// launch that fuses the update into its epilogue; it returns the site's
+// contribution to <r, r> (of the values as stored). Also the store of a site
+// of t = Q p with its squared norm, for the dslash launch that fuses
+// <p, A p> = |t|^2 into its epilogue.
 #pragma once
 
 #include "fields.h"
@@ -114,6 +116,39 @@ __device__ __forceinline__ double cg_site_update(float4* __restrict__ x, h8* __r
 #pragma unroll
   for (int c = 0; c < 12; ++c) rv[c] = {fmar(-a, ap[c].re, rv[c].re), fmar(-a, ap[c].im, rv[c].im)};
   return store_half_site(r, s, rv);
+}
+
+// Stores a site of t = Q p (streaming stores, as the plain operator) and
+// returns its squared norm (of the values as stored).
+__device__ __forceinline__ double store_site_norm(double2* __restrict__ p, long V, int s,
+                                                  const cx<double> (&v)[12]) {
+  store_spinor(p, V, s, v);
+  double n = 0.0;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) n += fmar(v[c].re, v[c].re, v[c].im * v[c].im);
+  return n;
+}
+__device__ __forceinline__ double store_site_norm(float4* __restrict__ p, long V, int s,
+                                                  const cx<float> (&v)[12]) {
+  store_spinor(p, V, s, v);
+  return site_norm2(v);
+}
+__device__ __forceinline__ double store_site_norm(h8* __restrict__ p, long /*V*/, int s,
+                                                  const cx<float> (&v)[12]) {
+  h8 q[3];
+  const float m = half_quantise(v, q);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) __builtin_nontemporal_store(q[j], p + half_unit(s, j));
+  __builtin_nontemporal_store(m, reinterpret_cast<float*>(p) + half_scale_index(s));
+  double n = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double d = static_cast<float>(q[j][k]) * m;
+      n = fmar(d, d, n);
+    }
+  return n;
 }
 
 // alpha = <r, r> / <p, A p> and its failure flag from <p, A p> = t.

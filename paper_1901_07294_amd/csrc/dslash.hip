@@ -195,18 +195,19 @@ __device__ __forceinline__ double wave_total(double v) {
   return v;
 }
 
-// Doubles of LDS per lane group and right-hand side that the fused CG update
-// uses after the spinor slices: per-wave <r,r> sums of two steps (tiles of at
-// most 4 waves) and alpha.
-constexpr int kCgLds = 2 * 4 + 1;
+// Doubles of LDS per lane group and right-hand side that the fused CG work
+// uses after the spinor slices: per-wave sums of two steps (tiles of at most
+// 4 waves) and the per-wave sums of <p, A p>.
+constexpr int kCgLds = 2 * 4 + 4;
 
 // MAXT: launch bound. A workgroup holds p.gw groups of n = X * ny lanes of
 // one tile; each lane carries RB right-hand sides (links loaded once for
 // all), each with its own two LDS slices. The LDS slices hold spinors in the
 // arithmetic precision (FP32 for FP16 storage).
-// With CG the output is not stored: the epilogue applies the CG update of
-// cgf to the field slots instead (n must be a multiple of 64).
-template <typename T, bool C12, int MAXT, int RB, bool CG>
+// CGM (CG iterations, n a multiple of 64): kCgNorm stores the output and
+// leaves each tile slice's squared norm of it in cgf.rr; kCgUpdate does not
+// store the output but applies the CG update of cgf to the field slots.
+template <typename T, bool C12, int MAXT, int RB, int CGM>
 __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
     const typename Packed<T>::S* __restrict__ in, typename Packed<T>::S* __restrict__ out,
     const typename Packed<T>::L* __restrict__ links, Geo geo, Diag<typename Packed<T>::R> diags,
@@ -270,35 +271,34 @@ __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[r][c] = {R(0), R(0)};
 
-  // fused CG update: per lane group and right-hand side, kCgLds doubles after
-  // all spinor slices; alpha from the <p,Ap> partial sums, reduced by the
-  // group's first wave in a fixed order (the same in every workgroup), and
-  // recorded in the scalars by the workgroup of the field's first tile
+  // fused CG work: per lane group and right-hand side, kCgLds doubles after
+  // all spinor slices. For the update, alpha = <r,r> / <p,Ap>: every lane of
+  // the tile sums a strided share of the <p,Ap> partial sums and each wave
+  // its lanes (an order fixed by the tile size, which the lattice fixes);
+  // after the prologue's barrier every lane adds the wave sums in order, so
+  // all lanes of all workgroups get the same alpha
   using XV = typename std::conditional<sizeof(R) == 8, double2, float4>::type;
   double* cgs = reinterpret_cast<double*>(reinterpret_cast<SV*>(smem) + p.gw * 2 * RB * kPlanes * n) +
                 slot * RB * kCgLds;
-  if constexpr (CG) {
-    if (tid < 64) {
+  double alpha[RB];
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const int k = diags.idx[rhs0 + r];
-        const double* pp = cgf.pap + static_cast<long>(k) * cgf.npap;
-        double t = 0.0;
-        for (int i = tid; i < cgf.npap; i += 64) t += pp[i];
-        t = wave_total(t);
-        if (tid == 0) {
-          double* sc = cgf.scal + static_cast<long>(k) * kScalars;
-          bool flag = false;
-          const double a = cg_alpha(t, sc[kRr], &flag);
-          cgs[r * kCgLds + 8] = a;
-          if (b == 0) {  // the field's first tile: one workgroup per field
-            sc[kPap] = t;
-            sc[kAlpha] = a;
-            sc[kRrPrev] = sc[kRr];
-            if (flag) sc[kFlag] = 1.0;
-          }
-        }
+  for (int r = 0; r < RB; ++r) alpha[r] = 0.0;
+  if constexpr (CGM == kCgUpdate) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const double* pp = cgf.pap + static_cast<long>(diags.idx[rhs0 + r]) * cgf.npap;
+      double t = 0.0;
+      int i = tid;
+      for (; i + 3 * n < cgf.npap; i += 4 * n) {  // four loads in flight, added in order
+        const double a0 = pp[i], a1 = pp[i + n], a2 = pp[i + 2 * n], a3 = pp[i + 3 * n];
+        t += a0;
+        t += a1;
+        t += a2;
+        t += a3;
       }
+      for (; i < cgf.npap; i += n) t += pp[i];
+      t = wave_total(t);
+      if ((tid & 63) == 0) cgs[r * kCgLds + 8 + (tid >> 6)] = t;
     }
   }
 
@@ -317,6 +317,23 @@ __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
     }
   }
   __syncthreads();
+  if constexpr (CGM == kCgUpdate) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      double t = 0.0;
+      for (int w = 0; w < n / 64; ++w) t += cgs[r * kCgLds + 8 + w];
+      const long k = diags.idx[rhs0 + r];
+      double* sc = cgf.scal + k * kScalars;
+      bool flag = false;
+      alpha[r] = cg_alpha(t, sc[kRr], &flag);
+      if (tid == 0 && b == 0) {  // the field's first tile: one workgroup per field
+        sc[kPap] = t;
+        sc[kAlpha] = alpha[r];
+        sc[kRrPrev] = sc[kRr];
+        if (flag) sc[kFlag] = 1.0;
+      }
+    }
+  }
 
   for (int t = t0; t < t1; ++t) {
     const int f = (t - t0) & 1;  // the buffer holding slice t
@@ -366,12 +383,16 @@ __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
       lds_load_spinor(cur[r], n, tid, psi);
       cx<R> o[12];
       epilogue(psi, acc[r], diag[r], gamma5, o);
-      if constexpr (CG) {
+      if constexpr (CGM == kCgUpdate) {
         const long k = diags.idx[rhs0 + r];
         double v = cg_site_update(static_cast<XV*>(cgf.x) + k * cgf.xstride,
                                   const_cast<GS*>(reinterpret_cast<const GS*>(cgf.r)) + k * stride,
                                   reinterpret_cast<const GS*>(cgf.p) + k * stride, V, st, o,
-                                  cgs[r * kCgLds + 8]);
+                                  alpha[r]);
+        v = wave_total(v);
+        if ((tid & 63) == 0) cgs[r * kCgLds + 4 * ((t - t0) & 1) + (tid >> 6)] = v;
+      } else if constexpr (CGM == kCgNorm) {
+        double v = store_site_norm(outr[r], V, st, o);
         v = wave_total(v);
         if ((tid & 63) == 0) cgs[r * kCgLds + 4 * ((t - t0) & 1) + (tid >> 6)] = v;
       } else {
@@ -389,8 +410,8 @@ __global__ __launch_bounds__(MAXT) void dslash_march_kernel(
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[r][c] = nacc[r][c];
     __syncthreads();
-    if constexpr (CG) {
-      // <r,r> of this tile slice: its waves in order (the next write to these
+    if constexpr (CGM != kCgNone) {
+      // the squared norm of this tile slice (Q p or r): its waves in order (the next write to these
       // words is two steps on, behind the next barrier)
       if (tid == 0) {
         const long ts = (static_cast<long>(t) * geo.Z + z) * p.ytiles + yt;
@@ -472,7 +493,7 @@ MarchParams march_params(const Geo& geo, size_t real_bytes, int nrhs) {
   return p;
 }
 
-template <typename T, bool C12, int MAXT, int RB, bool CG>
+template <typename T, bool C12, int MAXT, int RB, int CGM>
 hipError_t launch_march_t(const void* in, void* out, const void* links, const Geo& geo,
                           const Diag<typename Packed<T>::R>& diag, long stride, int g5,
                           const MarchParams& p, const CgFuse& f, hipStream_t st) {
@@ -481,38 +502,38 @@ hipError_t launch_march_t(const void* in, void* out, const void* links, const Ge
   using R = typename Packed<T>::R;
   const int n = geo.X * p.ny;
   size_t lds = static_cast<size_t>(p.gw) * RB * march_lds_bytes(n, sizeof(R));
-  if (CG) lds += static_cast<size_t>(p.gw) * RB * kCgLds * sizeof(double);
+  if (CGM != kCgNone) lds += static_cast<size_t>(p.gw) * RB * kCgLds * sizeof(double);
   if (lds > kLdsBytes) return hipErrorInvalidValue;
   // raise the kernel's dynamic LDS limit once to the whole LDS of a CU
   static std::atomic<int> attr_set{0};
   if (!attr_set.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&dslash_march_kernel<T, C12, MAXT, RB, CG>),
+        reinterpret_cast<const void*>(&dslash_march_kernel<T, C12, MAXT, RB, CGM>),
         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
     if (e != hipSuccess) return e;
     attr_set.store(1, std::memory_order_release);
   }
   const unsigned nb = static_cast<unsigned>((p.nrhs / (p.gw * RB)) * p.ytiles * geo.Z *
                                             ((geo.T + p.tb - 1) / p.tb));
-  dslash_march_kernel<T, C12, MAXT, RB, CG><<<nb, p.gw * n, lds, st>>>(
+  dslash_march_kernel<T, C12, MAXT, RB, CGM><<<nb, p.gw * n, lds, st>>>(
       static_cast<const SV*>(in), static_cast<SV*>(out), static_cast<const LV*>(links), geo, diag,
       stride, g5, p, f);
   return hipGetLastError();
 }
 
-template <typename T, bool C12, bool CG>
+template <typename T, bool C12, int CGM>
 hipError_t launch_march(const void* in, void* out, const void* links, const Geo& geo,
                         const Diag<typename Packed<T>::R>& diag, long stride, int g5,
                         const MarchParams& p, const CgFuse& f, hipStream_t st) {
   if constexpr (sizeof(typename Packed<T>::R) == 4) {
     if (p.rb == 2)  // two right-hand sides per lane: one lane group per workgroup
-      return launch_march_t<T, C12, kMarchMaxThreads, 2, CG>(in, out, links, geo, diag, stride, g5, p,
+      return launch_march_t<T, C12, kMarchMaxThreads, 2, CGM>(in, out, links, geo, diag, stride, g5, p,
                                                              f, st);
     if (p.gw > 1)
-      return launch_march_t<T, C12, kMarchMultiThreads, 1, CG>(in, out, links, geo, diag, stride, g5,
+      return launch_march_t<T, C12, kMarchMultiThreads, 1, CGM>(in, out, links, geo, diag, stride, g5,
                                                                p, f, st);
   }
-  return launch_march_t<T, C12, kMarchMaxThreads, 1, CG>(in, out, links, geo, diag, stride, g5, p, f,
+  return launch_march_t<T, C12, kMarchMaxThreads, 1, CGM>(in, out, links, geo, diag, stride, g5, p, f,
                                                          st);
 }
 
@@ -539,7 +560,8 @@ MarchParams with_tuning(MarchParams p, const MarchTuning& t) {
   return p;
 }
 
-// cg: the fused CG update (the march kernel only; nullptr for a plain apply).
+// cg: a CG iteration's fused work (the march kernel only; nullptr for a plain
+// apply): cg->mode kCgNorm or kCgUpdate.
 template <typename T, bool C12>
 hipError_t launch_typed(const wd_gauge* g, const void* in, void* out, const Geo& geo,
                         const double* masses, int nrhs, const int* fields, int g5,
@@ -559,12 +581,17 @@ hipError_t launch_typed(const wd_gauge* g, const void* in, void* out, const Geo&
     if (cg != nullptr) {
       if constexpr (sizeof(R) == 4) {
         if ((geo.X * p.ny) % 64 != 0) return hipErrorInvalidValue;
-        return launch_march<T, C12, true>(in, nullptr, g->links, geo, diag, stride, g5, p, *cg, st);
+        if (cg->mode == kCgNorm)
+          return launch_march<T, C12, kCgNorm>(in, out, g->links, geo, diag, stride, g5, p, *cg, st);
+        if (cg->mode == kCgUpdate)
+          return launch_march<T, C12, kCgUpdate>(in, nullptr, g->links, geo, diag, stride, g5, p, *cg,
+                                                 st);
+        return hipErrorInvalidValue;
       } else {
         return hipErrorInvalidValue;
       }
     }
-    return launch_march<T, C12, false>(in, out, g->links, geo, diag, stride, g5, p, CgFuse{}, st);
+    return launch_march<T, C12, kCgNone>(in, out, g->links, geo, diag, stride, g5, p, CgFuse{}, st);
   }
   if (cg != nullptr) return hipErrorInvalidValue;
   return launch_site<T, C12>(in, out, g->links, geo, diag, nrhs, stride, g5, st);
@@ -616,8 +643,8 @@ int cg_fuse_slices(const int32_t dims[4], int prec) {
 }
 
 hipError_t launch_dslash_cg(const wd_gauge* g, const double* masses, int nrhs, const int* fields,
-                            const void* in, const CgFuse& f, hipStream_t st) {
-  return launch_any(g, masses, nrhs, fields, in, nullptr, WD_FLAG_GAMMA5, nullptr, &f, st);
+                            const void* in, void* out, const CgFuse& f, hipStream_t st) {
+  return launch_any(g, masses, nrhs, fields, in, out, WD_FLAG_GAMMA5, nullptr, &f, st);
 }
 
 hipError_t launch_dslash(const wd_gauge* g, double mass, const void* in, void* out, int flags,

@@ -101,18 +101,22 @@ hipError_t launch_dslash_tuned(const wd_gauge* g, const double* masses, int nrhs
 // The autotuner's choice registered for (dims, prec, c12, nrhs), if any.
 bool tuned_lookup(const int32_t dims[4], int prec, int c12, int nrhs, MarchTuning* t);
 
-// The CG vector update fused into the second application of Q in an
-// iteration: the dslash epilogue uses Q t = A p at once for x += alpha p and
-// r -= alpha A p (alpha = <r,r> / <p,Ap> reduced from pap) instead of storing
-// it, and leaves the <r,r> partial sums of each tile slice (a tile's x rows
-// at one z and t, so the grouping is fixed by the lattice, not the launch).
+// Work of a CG iteration fused into its two applications of Q, as a mode of
+// the t-marching kernel. kCgNorm (first application, t = Q p): t is stored
+// and each tile slice (a tile's x rows at one z and t, so the grouping is
+// fixed by the lattice, not the launch) leaves its |t|^2 = <p, A p> partial
+// sum in rr. kCgUpdate (second application, A p = Q t): A p is used at once
+// for x += alpha p and r -= alpha A p (alpha = <r,r> / <p,Ap> reduced from
+// pap) instead of being stored, and each tile slice leaves its <r,r>.
+enum : int { kCgNone = 0, kCgNorm = 1, kCgUpdate = 2 };
 struct CgFuse {
+  int mode;           // kCgNorm or kCgUpdate
   void* x;            // FP64 solution (FP64 vectors) or FP32 accumulator x_lo
   void* r;            // residual, inner precision
   const void* p;      // search direction, inner precision
   const double* pap;  // <p, A p> partial sums, npap per field slot
   int npap;
-  double* rr;         // out: <r, r> per tile slice, nslices per field slot
+  double* rr;         // out: |t|^2 or <r, r> per tile slice, nslices per field slot
   int nslices;
   double* scal;       // per field slot scalars (kScalars doubles)
   long xstride;       // 16-byte elements of x per field slot
@@ -121,9 +125,10 @@ struct CgFuse {
 // where it does not apply (FP64, the one-site-per-lane kernel, or tiles that
 // are not whole waves).
 int cg_fuse_slices(const int32_t dims[4], int prec);
-// Q = gamma5 D(masses[i]) on field fields[i] of `in`, fused with the CG
-// update above for the same field slots (cg_fuse_slices must be > 0).
+// Q = gamma5 D(masses[i]) on field fields[i] of `in` (into `out` for
+// kCgNorm), fused with the work of f.mode for the same field slots
+// (cg_fuse_slices must be > 0).
 hipError_t launch_dslash_cg(const wd_gauge* g, const double* masses, int nrhs, const int* fields,
-                            const void* in, const CgFuse& f, hipStream_t s);
+                            const void* in, void* out, const CgFuse& f, hipStream_t s);
 
 }  // namespace wd
