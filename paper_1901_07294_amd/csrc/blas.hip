@@ -26,6 +26,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// This thread's share of pp[0..np): pp[threadIdx.x + kThreads * j] added in
+// order of j, with four loads in flight.
+__device__ __forceinline__ double strided_sum(const double* __restrict__ pp, int np) {
+  double s = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * kThreads < np; i += 4 * kThreads) {
+    const double a0 = pp[i], a1 = pp[i + kThreads], a2 = pp[i + 2 * kThreads], a3 = pp[i + 3 * kThreads];
+    s += a0;
+    s += a1;
+    s += a2;
+    s += a3;
+  }
+  for (; i < np; i += kThreads) s += pp[i];
+  return s;
+}
+
 // Sum of v over the workgroup, combined in a fixed order; valid in thread 0.
 __device__ __forceinline__ double block_sum(double v) {
   __shared__ double part[kThreads / 64];
@@ -46,8 +62,7 @@ __device__ __forceinline__ double block_sum(double v) {
 __device__ __forceinline__ double alpha_from_partials(const double* __restrict__ pp, int np,
                                                       double* sc) {
   __shared__ double s_alpha;
-  double t = 0.0;
-  for (int i = threadIdx.x; i < np; i += kThreads) t += pp[i];
+  double t = strided_sum(pp, np);
   t = block_sum(t);
   if (threadIdx.x == 0) {
     bool flag = !isfinite(t);
@@ -78,16 +93,7 @@ __device__ __forceinline__ double alpha_from_partials(const double* __restrict__
 __device__ __forceinline__ double beta_from_partials(const double* __restrict__ pp, int np,
                                                      double* sc) {
   __shared__ double s_beta;
-  double s = 0.0;
-  int i = threadIdx.x;
-  for (; i + 3 * kThreads < np; i += 4 * kThreads) {  // four loads in flight, added in order
-    const double a0 = pp[i], a1 = pp[i + kThreads], a2 = pp[i + 2 * kThreads], a3 = pp[i + 3 * kThreads];
-    s += a0;
-    s += a1;
-    s += a2;
-    s += a3;
-  }
-  for (; i < np; i += kThreads) s += pp[i];
+  double s = strided_sum(pp, np);
   s = block_sum(s);
   if (threadIdx.x == 0) {
     const double old = sc[kRrPrev];
@@ -387,8 +393,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(const double* __rest
                                                             int nparts, RhsSet set, int mode,
                                                             double* __restrict__ scal) {
   const int k = set.idx[blockIdx.x];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kThreads) s += partials[k * nparts + i];
+  double s = strided_sum(partials + k * nparts, nparts);
   s = block_sum(s);
   if (threadIdx.x != 0) return;
   double* sc = scal + k * kScalars;
