@@ -46,13 +46,13 @@ def compulsory_bytes(prec: str, c12: bool) -> int:
 TRAFFIC = {
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated KiB per dispatch), measured for
     # the kernel sources hashed below, per launch "tb,gw,group,rb" the bytes belong to
-    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "03e7eb9a06701504", "launches": {
-        "32,1,32,1": 2255586858,    # 904,774.7 / 393,216.0
-        "16,1,64,1": 2372516085}},  # 961,870.5 / 393,216.0
-    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "03e7eb9a06701504", "launches": {
-        "16,1,64,1": 1123794230}},  # 450,434.6 / 196,608.0
-    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "03e7eb9a06701504", "launches": {
-        "4,1,256,1": 622216671}},   # 250,574.8 / 106,496.0
+    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "eb39584573490569", "launches": {
+        "32,1,32,1": 2248245380,    # 901,190.0 / 393,216.0
+        "16,1,64,1": 2380491247}},  # 965,764.8 / 393,216.0
+    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "eb39584573490569", "launches": {
+        "16,1,64,1": 1123524705}},  # 450,303.0 / 196,608.0
+    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "eb39584573490569", "launches": {
+        "4,1,256,1": 621823766}},   # 250,383.0 / 106,496.0
 }
 KERNEL_SOURCES = ["paper_1901_07294_amd/csrc/dslash.hip", "paper_1901_07294_amd/csrc/stencil.h",
                   "paper_1901_07294_amd/csrc/fields.h", "paper_1901_07294_amd/csrc/cplx.h"]

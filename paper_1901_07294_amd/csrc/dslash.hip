@@ -207,8 +207,18 @@ constexpr int kCgLds = 2 * 4 + 4;
 // CGM (CG iterations, n a multiple of 64): kCgNorm stores the output and
 // leaves each tile slice's squared norm of it in cgf.rr; kCgUpdate does not
 // store the output but applies the CG update of cgf to the field slots.
+// Three waves per SIMD (the plain FP32-arithmetic kernel's occupancy) are
+// kept, at the cost of a few spilled registers, where that was measured to
+// pay: Q p with its norm in FP32 storage, and the update in FP16 storage.
+template <int CGM, typename T, int RB>
+constexpr int march_waves_per_eu() {
+  return RB == 1 && ((CGM == kCgNorm && sizeof(T) == 4) || (CGM == kCgUpdate && sizeof(T) == 2)) ? 3
+                                                                                                : 1;
+}
+
 template <typename T, bool C12, int MAXT, int RB, int CGM>
-__global__ __launch_bounds__(MAXT) void dslash_march_kernel(
+__global__ __launch_bounds__(MAXT)
+__attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dslash_march_kernel(
     const typename Packed<T>::S* __restrict__ in, typename Packed<T>::S* __restrict__ out,
     const typename Packed<T>::L* __restrict__ links, Geo geo, Diag<typename Packed<T>::R> diags,
     long stride, int gamma5, MarchParams p, CgFuse cgf) {
