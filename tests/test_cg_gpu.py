@@ -227,3 +227,34 @@ def test_cg_mixed_on_tiles_that_are_not_whole_waves(inner):
         rc1, x1, _, _ = solve(U, [masses[k]], bs[k][None], INNER[inner])
         assert rc1 == w.WD_OK
         assert np.array_equal(x1[0], xs[k])
+
+
+@pytest.mark.parametrize("inner", ["fp32", "fp16"])
+def test_cg_results_independent_of_the_launch_shape(inner, tmp_path):
+    """The fused CG launches sum their partial sums per tile slice, so a solve
+    gives the same bits whatever launch the tuning registry holds for its
+    lattice: two right-hand sides per lane, or two lane groups per
+    workgroup, against the default (tuning files loaded for the key)."""
+    dims = (8, 8, 4, 4)
+    U = li.near_unity_gauge(dims, 95, 0.3)
+    bs = li.gaussian_spinors(dims, [96, 97])
+    masses = [0.05, 0.3]
+    prec = INNER[inner]
+    w.wd_tune_reset()
+    try:
+        rc, ref, _, _ = solve(U, masses, bs, prec)
+        assert rc == w.WD_OK
+        header_file = tmp_path / "empty.txt"
+        w.wd_tune_save(str(header_file))
+        header = header_file.read_text().splitlines()[0]
+        for tb, gw, group, rb in ((1, 1, 0, 2), (2, 2, 0, 1), (4, 1, 0, 1)):
+            path = tmp_path / f"t{tb}{gw}{rb}.txt"
+            path.write_text(f"{header}\n{dims[0]} {dims[1]} {dims[2]} {dims[3]} {prec} 0 2 {tb} {gw} {group} {rb}\n")
+            w.wd_tune_reset()
+            w.wd_tune_load(str(path))
+            assert w.wd_tune_lookup(dims, prec, 0, 2) == (tb, gw, group, rb)
+            rc, xs, _, _ = solve(U, masses, bs, prec)
+            assert rc == w.WD_OK
+            assert np.array_equal(xs, ref), (tb, gw, group, rb)
+    finally:
+        w.wd_tune_reset()
