@@ -75,6 +75,8 @@ def parse(argv=None):
     ap.add_argument("--c12", action="store_true", help="12-real link compression")
     ap.add_argument("--dims", type=str, default=",".join(map(str, DIMS)))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=80,
+                    help="requests in the serving measurement (capacity and each load level)")
     ap.add_argument("--tuning", type=str, default=None,
                     help="TB,GW,GROUP,RB: time the operator with this launch instead of the "
                          "autotuner's choice (profiling runs pin it)")
@@ -404,7 +406,9 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
                     done[t] = (rc, res, live.pop(t))
 
         t0 = time.time()
-        for (i, m), a in zip(reqs, arrivals):
+        for j, ((i, m), a) in enumerate(zip(reqs, arrivals)):
+            if j and j % 100 == 0:
+                print(f"[bench] serving: {j} of {len(reqs)} submitted", file=sys.stderr, flush=True)
             while a is not None and time.time() - t0 < a:
                 poll()
                 time.sleep(0.0005)
@@ -627,7 +631,7 @@ def main(argv=None):
     serve = None
     if not args.no_serve:
         print("[bench] request server", file=sys.stderr, flush=True)
-        serve = bench_serve(torch, w, li, DeviceGauge)
+        serve = bench_serve(torch, w, li, DeviceGauge, n_req=args.serve_requests)
 
     cpu = None
     if not args.no_cpu_baseline:
