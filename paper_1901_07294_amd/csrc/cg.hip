@@ -52,7 +52,7 @@ CgLayout cg_layout(const int32_t dims[4], int slots, int inner) {
   w.r = o; o += lo;
   w.p = o; o += lo;
   w.t = o; o += lo;
-  if (w.nslices == 0) {
+  if (w.nslices == 0 || inner == WD_FP64) {  // FP64 keeps A p (the update is not fused)
     w.ap = o;
     o += lo;
   }
@@ -130,6 +130,29 @@ int CgEngine::start(const RhsSet& set, bool x0_given) {
 int CgEngine::iterate(const RhsSet& set) {
   double m[kMaxRhs];
   for (int i = 0; i < set.n; ++i) m[i] = masses_[set.idx[i]];
+  if (lay_.nslices > 0 && inner_ == WD_FP64) {
+    // t = Q p with <p, A p> = |t|^2 summed per tile slice in the same launch;
+    // A p = Q t; the x, r update (reducing those sums to alpha) and the p
+    // update as separate kernels
+    CgFuse f{};
+    f.mode = kCgNorm;
+    f.rr = paps_;
+    f.nslices = lay_.nslices;
+    int rc = launch_status(launch_dslash_cg(glo_, m, set.n, set.idx, at(ws_, lay_.p), at(ws_, lay_.t), f,
+                                            st_), "cg: Q p with |Q p|^2");
+    if (rc == WD_OK)
+      rc = launch_status(launch_dslash_multi(glo_, m, set.n, set.idx, at(ws_, lay_.t), at(ws_, lay_.ap),
+                                             WD_FLAG_GAMMA5, st_), "cg: Q Q p");
+    int nrr = 0;
+    if (rc == WD_OK)
+      rc = launch_status(blas_update_xr(x_, at(ws_, lay_.r), at(ws_, lay_.p), at(ws_, lay_.ap), inner_,
+                                        nlo_, n32_, V_, set, paps_, lay_.nslices, partials_, &nrr, scal_,
+                                        st_), "cg: x, r");
+    if (rc == WD_OK)
+      rc = launch_status(blas_update_p(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, V_, set, partials_,
+                                       nrr, scal_, st_), "cg: p");
+    return rc;
+  }
   if (lay_.nslices > 0) {
     // t = Q p, with <p, A p> = |t|^2 summed per tile slice in the same launch;
     // then Q t = A p used at once for x += alpha p, r -= alpha A p, with

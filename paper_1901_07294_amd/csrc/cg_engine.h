@@ -11,8 +11,8 @@ namespace wd {
 
 // Offsets (bytes) of a CG workspace for `slots` right-hand sides. Where the
 // iteration's vector work is fused into its applications of Q (nslices > 0),
-// A p is never stored, and paps and rr hold the |Q p|^2 and <r,r> partial
-// sums of the tile slices.
+// paps and rr hold the |Q p|^2 and <r,r> partial sums of the tile slices, and
+// (FP32 arithmetic, where the update is fused too) A p is never stored.
 struct CgLayout {
   size_t bytes = 0;
   size_t r_hi = 0, t_hi = 0, x_lo = 0, r = 0, p = 0, t = 0, ap = 0, partials = 0, pap = 0, scal = 0,

@@ -589,17 +589,15 @@ hipError_t launch_typed(const wd_gauge* g, const void* in, void* out, const Geo&
     if (force != nullptr) p = with_tuning(p, *force);
     else if (tuned_lookup(g->dims, g->prec, g->c12, nrhs, &t)) p = with_tuning(p, t);
     if (cg != nullptr) {
-      if constexpr (sizeof(R) == 4) {
-        if ((geo.X * p.ny) % 64 != 0) return hipErrorInvalidValue;
-        if (cg->mode == kCgNorm)
-          return launch_march<T, C12, kCgNorm>(in, out, g->links, geo, diag, stride, g5, p, *cg, st);
+      if ((geo.X * p.ny) % 64 != 0) return hipErrorInvalidValue;
+      if (cg->mode == kCgNorm)
+        return launch_march<T, C12, kCgNorm>(in, out, g->links, geo, diag, stride, g5, p, *cg, st);
+      if constexpr (sizeof(R) == 4) {  // the update is fused with FP32 arithmetic only
         if (cg->mode == kCgUpdate)
           return launch_march<T, C12, kCgUpdate>(in, nullptr, g->links, geo, diag, stride, g5, p, *cg,
                                                  st);
-        return hipErrorInvalidValue;
-      } else {
-        return hipErrorInvalidValue;
       }
+      return hipErrorInvalidValue;
     }
     return launch_march<T, C12, kCgNone>(in, out, g->links, geo, diag, stride, g5, p, CgFuse{}, st);
   }
@@ -640,11 +638,11 @@ hipError_t launch_dslash_multi(const wd_gauge* g, const double* masses, int nrhs
   return launch_any(g, masses, nrhs, fields, in, out, flags, nullptr, nullptr, st);
 }
 
-// FP32 arithmetic only: the FP64 kernel holds one wave per SIMD, and the x, r
-// update in its epilogue cost more than the separate update kernel it saves
-// (24^4 FP64 CG 46.5 -> 47.9 ms per solve).
+// (With FP64 vectors the engine fuses only the norm: the FP64 kernel holds one
+// wave per SIMD, and the x, r update in its epilogue cost more than the
+// separate update kernel it saves: 24^4 FP64 CG 46.5 -> 47.9 ms per solve.)
 int cg_fuse_slices(const int32_t dims[4], int prec) {
-  if (WD_DSLASH_KERNEL != 0 || prec == WD_FP64) return 0;
+  if (WD_DSLASH_KERNEL != 0) return 0;
   const Geo geo = make_geo(dims);
   const MarchParams p = march_params(geo, real_bytes_of(prec), 1);
   if (p.ny == 0 || (geo.X * p.ny) % 64 != 0) return 0;

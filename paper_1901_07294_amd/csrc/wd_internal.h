@@ -121,9 +121,9 @@ struct CgFuse {
   double* scal;       // per field slot scalars (kScalars doubles)
   long xstride;       // 16-byte elements of x per field slot
 };
-// Tile slices of the fused update on a lattice in an inner precision, or 0
-// where it does not apply (FP64, the one-site-per-lane kernel, or tiles that
-// are not whole waves).
+// Tile slices of the fused work on a lattice in a precision, or 0 where it
+// does not apply (the one-site-per-lane kernel, or tiles that are not whole
+// waves). kCgUpdate exists for FP32 arithmetic (FP32 and FP16 storage) only.
 int cg_fuse_slices(const int32_t dims[4], int prec);
 // Q = gamma5 D(masses[i]) on field fields[i] of `in` (into `out` for
 // kCgNorm), fused with the work of f.mode for the same field slots
