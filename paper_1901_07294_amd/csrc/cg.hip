@@ -23,8 +23,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "cg_engine.h"
@@ -242,6 +245,8 @@ RhsSet set_of(const std::vector<int>& ks) {
 // Chunks of CG iterations captured as HIP graphs and replayed: one graph per
 // (set of active right-hand sides, chunk length). The scalars never leave the
 // device inside a chunk, so a replay needs no host work between iterations.
+// (The scalar copy after a chunk stays outside the graph: as the graph's last
+// node it delayed the host's view of completion.)
 class ChunkGraphs {
  public:
   explicit ChunkGraphs(hipStream_t st) : st_(st) {}
@@ -307,6 +312,65 @@ class OwnStream {
   bool ok_ = true;
 };
 
+// Page-locked host buffers for the scalars the synchronous solver reads after
+// each chunk of iterations (a copy into pageable memory is staged through the
+// runtime; with page-locked memory the graph-replayed 8^4 solve went from 5.2
+// to 5.0 ms). Each holds kMaxRhs slots; buffers are kept for the life of the
+// process and reused by later solves, except one whose last copy may not have
+// completed (a device error), which is dropped.
+class HostScalars {
+ public:
+  HostScalars() {
+    {
+      std::lock_guard<std::mutex> lk(mu());
+      if (!pool().empty()) {
+        p_ = pool().back();
+        pool().pop_back();
+      }
+    }
+    if (p_ == nullptr && hipHostMalloc(reinterpret_cast<void**>(&p_), kBytes, hipHostMallocPortable) != hipSuccess)
+      p_ = nullptr;
+    if (p_ != nullptr) std::memset(p_, 0, kBytes);
+  }
+  ~HostScalars() {
+    if (p_ == nullptr || !reusable_) return;
+    std::lock_guard<std::mutex> lk(mu());
+    pool().push_back(p_);
+  }
+  HostScalars(const HostScalars&) = delete;
+  HostScalars& operator=(const HostScalars&) = delete;
+  double* get() const { return p_; }
+  void drop() { reusable_ = false; }
+
+ private:
+  static constexpr size_t kBytes = sizeof(double) * kMaxRhs * kScalars;
+  static std::mutex& mu() {
+    static std::mutex m;
+    return m;
+  }
+  static std::vector<double*>& pool() {
+    static auto* v = new std::vector<double*>;  // never destroyed: process lifetime
+    return *v;
+  }
+  double* p_ = nullptr;
+  bool reusable_ = true;
+};
+
+// Waits for the stream by polling it: after a blocking wait the host takes
+// tens of microseconds to wake up, during which the device idles, once per
+// chunk of iterations. Ends when the stream's work has completed or failed.
+// Used for eager chunks (24^4 FP16-storage inner 62.5-63.0 -> 65.2 solves/s,
+// 8^4 FP32 inner 5.3 -> 4.9 ms per solve); after a graph replay polling
+// measured slower than a blocking wait (8^4: 5.0 -> 5.4-6.1 ms), so replays
+// keep the blocking wait.
+hipError_t poll_stream(hipStream_t st) {
+  for (;;) {
+    const hipError_t e = hipStreamQuery(st);
+    if (e != hipErrorNotReady) return e;
+    std::this_thread::yield();
+  }
+}
+
 // The synchronous solver: all right-hand sides start together; every
 // check_every iterations the host reads the scalars, recomputes the true
 // residual of those that need it, and drops the finished ones. With
@@ -325,14 +389,19 @@ int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, i
   if (own) graphs = std::make_unique<ChunkGraphs>(st);
   CgEngine eng(ghi, glo, prm.inner, nrhs, b, x, ws, st);
   for (int k = 0; k < nrhs; ++k) eng.set_mass(k, masses[k]);
-  std::vector<double> hs(static_cast<size_t>(nrhs) * kScalars, 0.0);
-  auto sc = [&](int k) { return hs.data() + static_cast<size_t>(k) * kScalars; };
-  auto read = [&]() {
-    int rc = eng.fetch_scalars(hs.data());
-    if (rc != WD_OK) return rc;
-    const hipError_t e = hipStreamSynchronize(st);
-    return e == hipSuccess ? WD_OK
-                           : set_error(WD_ERR_DEVICE, "cg: device error: %s", hipGetErrorString(e));
+  HostScalars hs;
+  if (hs.get() == nullptr) return set_error(WD_ERR_NOMEM, "cg: cannot allocate page-locked host memory");
+  auto sc = [&](int k) { return hs.get() + static_cast<size_t>(k) * kScalars; };
+  auto read = [&]() -> int {
+    const int rc = eng.fetch_scalars(hs.get());
+    if (rc != WD_OK) {
+      hs.drop();
+      return rc;
+    }
+    const hipError_t e = graphs ? hipStreamSynchronize(st) : poll_stream(st);
+    if (e == hipSuccess) return WD_OK;
+    hs.drop();
+    return set_error(WD_ERR_DEVICE, "cg: device error: %s", hipGetErrorString(e));
   };
   std::vector<int> status(nrhs, WD_PENDING), iters(nrhs, 0), updates(nrhs, 0), all;
   for (int k = 0; k < nrhs; ++k) all.push_back(k);
