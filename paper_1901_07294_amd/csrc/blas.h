@@ -50,6 +50,16 @@ hipError_t blas_norm2_partials(const void* v, int prec, long n, long V, const Rh
 hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int prec, long n, long nlo32,
                           long V, const RhsSet& set, const double* pap, int npap, double* partials,
                           int* nrr, double* scal, hipStream_t st);
+// FP64 vectors, an iteration's vector work in two launches that read p once:
+// blas_update_r does r -= alpha Ap (alpha reduced from the npap partials in
+// pap, as blas_update_xr) and leaves the *nrr partial sums of the new <r,r> in
+// partials; blas_update_xp then does x += alpha p and p = r + beta p (beta
+// reduced from those partials, as blas_update_p). Same bits as blas_update_xr
+// followed by blas_update_p.
+hipError_t blas_update_r(void* r, const void* ap, long n, long V, const RhsSet& set, const double* pap,
+                         int npap, double* partials, int* nrr, double* scal, hipStream_t st);
+hipError_t blas_update_xp(void* x, void* p, const void* r, long n, const RhsSet& set, const double* rr,
+                          int nrr, double* scal, hipStream_t st);
 // x_hi += x_lo, then x_lo = 0
 hipError_t blas_flush_x(void* hi, void* lo, long nlo32, long nhi, const RhsSet& set, hipStream_t st);
 // p = r + beta p with beta = <r,r>_new / <r,r>_old, <r,r>_new reduced from the

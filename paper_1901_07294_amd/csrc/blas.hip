@@ -191,6 +191,63 @@ __global__ __launch_bounds__(kThreads) void update_xr_kernel(T* __restrict__ x, 
   if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
 }
 
+// FP64 vectors, first half of the vector work of an iteration: r -= alpha Ap
+// and the partial sums of the new |r|^2 (alpha reduced from the <p, A p>
+// partials, as in update_xr_kernel). The second half, update_xp_kernel,
+// updates x and p together, so p is read once per iteration.
+__global__ __launch_bounds__(kThreads) void update_r_kernel(double2* __restrict__ r,
+                                                            const double2* __restrict__ ap, long n,
+                                                            long V, RhsSet set, double* __restrict__ scal,
+                                                            const double* __restrict__ pap, int npap,
+                                                            double* __restrict__ partials) {
+  const int k = set.idx[blockIdx.y];
+  const double alpha = alpha_from_partials(pap + k * npap, npap, scal + k * kScalars);
+  double2* rk = r + k * n;
+  const double2* apk = ap + k * n;
+  double s = 0.0;
+  for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
+       e += static_cast<long>(gridDim.x) * kThreads) {
+    double2 re = rk[e];
+    const double2 ae = apk[e];
+    re.x = fmar(-alpha, ae.x, re.x);
+    re.y = fmar(-alpha, ae.y, re.y);
+    rk[e] = re;
+    if (real_site<12>(e, V)) s += norm2(re);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
+}
+
+// FP64 vectors: x += alpha p, then p = r + beta p, with alpha as workgroup 0 of
+// update_r_kernel recorded it (the value every workgroup there applied) and
+// beta reduced from that kernel's |r|^2 partials. Each element gets the
+// multiply-adds of update_xr_kernel and update_p_kernel, so the bits match.
+__global__ __launch_bounds__(kThreads) void update_xp_kernel(double2* __restrict__ x,
+                                                             double2* __restrict__ p,
+                                                             const double2* __restrict__ r, long n,
+                                                             RhsSet set, const double* __restrict__ rr,
+                                                             int nrr, double* __restrict__ scal) {
+  const int k = set.idx[blockIdx.y];
+  double* sc = scal + k * kScalars;
+  const double alpha = sc[kAlpha];  // not written by this kernel
+  const double beta = beta_from_partials(rr + k * nrr, nrr, sc);
+  double2* xk = x + k * n;
+  double2* pk = p + k * n;
+  const double2* rk = r + k * n;
+  for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
+       e += static_cast<long>(gridDim.x) * kThreads) {
+    double2 pe = pk[e];
+    const double2 re = rk[e];
+    double2 xe = xk[e];
+    xe.x = fmar(alpha, pe.x, xe.x);
+    xe.y = fmar(alpha, pe.y, xe.y);
+    pe.x = fmar(beta, pe.x, re.x);
+    pe.y = fmar(beta, pe.y, re.y);
+    xk[e] = xe;
+    pk[e] = pe;
+  }
+}
+
 // x_hi += x_lo (FP32 element j of a block holds FP64 elements 2j and 2j+1 of
 // the same sites), then x_lo = 0
 __global__ __launch_bounds__(kThreads) void flush_x_kernel(double2* __restrict__ hi,
@@ -469,6 +526,23 @@ hipError_t blas_update_xr(void* x, void* r, const void* p, const void* ap, int p
     update_xr_half_kernel<<<g, kThreads, 0, st>>>(static_cast<float4*>(x), static_cast<h8*>(r),
                                                   static_cast<const h8*>(p), static_cast<const h8*>(ap),
                                                   n, nlo32, V, set, scal, pap, npap, partials);
+  return hipGetLastError();
+}
+
+hipError_t blas_update_r(void* r, const void* ap, long n, long V, const RhsSet& set, const double* pap,
+                         int npap, double* partials, int* nrr, double* scal, hipStream_t st) {
+  const dim3 g = grid(n, set.n);
+  *nrr = static_cast<int>(g.x);
+  update_r_kernel<<<g, kThreads, 0, st>>>(static_cast<double2*>(r), static_cast<const double2*>(ap), n, V,
+                                          set, scal, pap, npap, partials);
+  return hipGetLastError();
+}
+
+hipError_t blas_update_xp(void* x, void* p, const void* r, long n, const RhsSet& set, const double* rr,
+                          int nrr, double* scal, hipStream_t st) {
+  update_xp_kernel<<<grid(n, set.n), kThreads, 0, st>>>(static_cast<double2*>(x), static_cast<double2*>(p),
+                                                        static_cast<const double2*>(r), n, set, rr, nrr,
+                                                        scal);
   return hipGetLastError();
 }
 

@@ -135,8 +135,8 @@ int CgEngine::iterate(const RhsSet& set) {
   for (int i = 0; i < set.n; ++i) m[i] = masses_[set.idx[i]];
   if (lay_.nslices > 0 && inner_ == WD_FP64) {
     // t = Q p with <p, A p> = |t|^2 summed per tile slice in the same launch;
-    // A p = Q t; the x, r update (reducing those sums to alpha) and the p
-    // update as separate kernels
+    // A p = Q t; then r -= alpha A p (reducing those sums to alpha), and x and
+    // p together (p is read once)
     CgFuse f{};
     f.mode = kCgNorm;
     f.rr = paps_;
@@ -148,12 +148,11 @@ int CgEngine::iterate(const RhsSet& set) {
                                              WD_FLAG_GAMMA5, st_), "cg: Q Q p");
     int nrr = 0;
     if (rc == WD_OK)
-      rc = launch_status(blas_update_xr(x_, at(ws_, lay_.r), at(ws_, lay_.p), at(ws_, lay_.ap), inner_,
-                                        nlo_, n32_, V_, set, paps_, lay_.nslices, partials_, &nrr, scal_,
-                                        st_), "cg: x, r");
+      rc = launch_status(blas_update_r(at(ws_, lay_.r), at(ws_, lay_.ap), nlo_, V_, set, paps_,
+                                       lay_.nslices, partials_, &nrr, scal_, st_), "cg: r");
     if (rc == WD_OK)
-      rc = launch_status(blas_update_p(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, V_, set, partials_,
-                                       nrr, scal_, st_), "cg: p");
+      rc = launch_status(blas_update_xp(x_, at(ws_, lay_.p), at(ws_, lay_.r), nlo_, set, partials_, nrr,
+                                        scal_, st_), "cg: x, p");
     return rc;
   }
   if (lay_.nslices > 0) {
@@ -195,8 +194,17 @@ int CgEngine::iterate(const RhsSet& set) {
                        "cg: pAp");
   // <r, r> likewise: partial sums in the x, r update, reduced (with beta) inside the p update
   int nrr = 0;
+  if (inner_ == WD_FP64) {  // r first, then x and p together (p read once)
+    if (rc == WD_OK)
+      rc = launch_status(blas_update_r(at(ws_, lay_.r), at(ws_, lay_.ap), nlo_, V_, set, pap_, npap,
+                                       partials_, &nrr, scal_, st_), "cg: r");
+    if (rc == WD_OK)
+      rc = launch_status(blas_update_xp(x_, at(ws_, lay_.p), at(ws_, lay_.r), nlo_, set, partials_, nrr,
+                                        scal_, st_), "cg: x, p");
+    return rc;
+  }
   if (rc == WD_OK)
-    rc = launch_status(blas_update_xr(inner_ == WD_FP64 ? x_ : at(ws_, lay_.x_lo), at(ws_, lay_.r),
+    rc = launch_status(blas_update_xr(at(ws_, lay_.x_lo), at(ws_, lay_.r),
                                       at(ws_, lay_.p), at(ws_, lay_.ap), inner_, nlo_, n32_, V_, set,
                                       pap_, npap, partials_, &nrr, scal_, st_), "cg: x, r");
   if (rc == WD_OK)
