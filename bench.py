@@ -46,13 +46,13 @@ def compulsory_bytes(prec: str, c12: bool) -> int:
 TRAFFIC = {
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated KiB per dispatch), measured for
     # the kernel sources hashed below, per launch "tb,gw,group,rb" the bytes belong to
-    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "5c9f8b259286d36a", "launches": {
-        "32,1,32,1": 2258892064,    # 906,366.6 / 393,216.0
-        "16,1,64,1": 2384636768}},  # 967,765.4 / 393,216.0
-    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "5c9f8b259286d36a", "launches": {
-        "16,1,64,1": 1122926080}},  # 449,999.8 / 196,608.0
-    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "5c9f8b259286d36a", "launches": {
-        "4,1,256,1": 622265664}},   # 250,592.7 / 106,496.0
+    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "5bb31f3eca42aa0b", "launches": {
+        "32,1,32,1": 2248531296,    # 901,307.7 / 393,216.0
+        "16,1,64,1": 2376253760}},  # 963,672.2 / 393,216.0
+    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "5bb31f3eca42aa0b", "launches": {
+        "16,1,64,1": 1123991360}},  # 450,519.9 / 196,608.0
+    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "5bb31f3eca42aa0b", "launches": {
+        "4,1,256,1": 622346976}},   # 250,632.4 / 106,496.0
 }
 KERNEL_SOURCES = ["paper_1901_07294_amd/csrc/dslash.hip", "paper_1901_07294_amd/csrc/stencil.h",
                   "paper_1901_07294_amd/csrc/fields.h", "paper_1901_07294_amd/csrc/cplx.h"]

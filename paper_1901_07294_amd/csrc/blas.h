@@ -60,6 +60,13 @@ hipError_t blas_update_r(void* r, const void* ap, long n, long V, const RhsSet& 
                          int npap, double* partials, int* nrr, double* scal, hipStream_t st);
 hipError_t blas_update_xp(void* x, void* p, const void* r, long n, const RhsSet& set, const double* rr,
                           int nrr, double* scal, hipStream_t st);
+// Mixed precision (FP32 or FP16-storage vectors), after the dslash launch that
+// applied r -= alpha Ap in its epilogue: x_lo += alpha p (alpha as that launch
+// recorded it; x_lo the FP32 accumulator, nlo32 16-byte elements per
+// right-hand side), then p = r + beta p with beta reduced from the nrr <r,r>
+// partial sums in rr; p is read once.
+hipError_t blas_update_xp_lo(void* x, void* p, const void* r, int prec, long n, long nlo32, long V,
+                             const RhsSet& set, const double* rr, int nrr, double* scal, hipStream_t st);
 // x_hi += x_lo, then x_lo = 0
 hipError_t blas_flush_x(void* hi, void* lo, long nlo32, long nhi, const RhsSet& set, hipStream_t st);
 // p = r + beta p with beta = <r,r>_new / <r,r>_old, <r,r>_new reduced from the

@@ -248,6 +248,41 @@ __global__ __launch_bounds__(kThreads) void update_xp_kernel(double2* __restrict
   }
 }
 
+// Mixed precision, FP32 vectors, after the dslash launch that applied
+// r -= alpha Ap in its epilogue: x_lo += alpha p, then p = r + beta p, with
+// alpha as that launch recorded it (the value all its workgroups applied) and
+// beta reduced from its <r,r> per tile slice. The multiply-adds are those of
+// update_xr_kernel and update_p_kernel, so the bits match.
+__global__ __launch_bounds__(kThreads) void update_xp_lo_kernel(float4* __restrict__ x,
+                                                                float4* __restrict__ p,
+                                                                const float4* __restrict__ r, long n,
+                                                                RhsSet set, const double* __restrict__ rr,
+                                                                int nrr, double* __restrict__ scal) {
+  const int k = set.idx[blockIdx.y];
+  double* sc = scal + k * kScalars;
+  const float a = static_cast<float>(sc[kAlpha]);  // not written by this kernel
+  const float b = static_cast<float>(beta_from_partials(rr + k * nrr, nrr, sc));
+  float4* xk = x + k * n;
+  float4* pk = p + k * n;
+  const float4* rk = r + k * n;
+  for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
+       e += static_cast<long>(gridDim.x) * kThreads) {
+    float4 pe = pk[e];
+    const float4 re = rk[e];
+    float4 xe = xk[e];
+    xe.x = fmar(a, pe.x, xe.x);
+    xe.y = fmar(a, pe.y, xe.y);
+    xe.z = fmar(a, pe.z, xe.z);
+    xe.w = fmar(a, pe.w, xe.w);
+    pe.x = fmar(b, pe.x, re.x);
+    pe.y = fmar(b, pe.y, re.y);
+    pe.z = fmar(b, pe.z, re.z);
+    pe.w = fmar(b, pe.w, re.w);
+    xk[e] = xe;
+    pk[e] = pe;
+  }
+}
+
 // x_hi += x_lo (FP32 element j of a block holds FP64 elements 2j and 2j+1 of
 // the same sites), then x_lo = 0
 __global__ __launch_bounds__(kThreads) void flush_x_kernel(double2* __restrict__ hi,
@@ -403,6 +438,32 @@ __global__ __launch_bounds__(kThreads) void update_xr_half_kernel(
   }
   s = block_sum(s);
   if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
+}
+
+// Mixed precision, FP16-storage vectors, after the dslash launch that applied
+// r -= alpha Ap: x_lo += alpha p (x_lo FP32, nlo32 elements per right-hand
+// side), then p = r + beta p requantised; alpha and beta as update_xp_lo_kernel.
+__global__ __launch_bounds__(kThreads) void update_xp_half_kernel(float4* __restrict__ x, h8* __restrict__ p,
+                                                                  const h8* __restrict__ r, long units,
+                                                                  long nlo32, long V, RhsSet set,
+                                                                  const double* __restrict__ rr, int nrr,
+                                                                  double* __restrict__ scal) {
+  const int k = set.idx[blockIdx.y];
+  double* sc = scal + k * kScalars;
+  const float a = static_cast<float>(sc[kAlpha]);  // not written by this kernel
+  const float b = static_cast<float>(beta_from_partials(rr + k * nrr, nrr, sc));
+  float4* xk = x + k * nlo32;
+  h8* pk = p + k * units;
+  const h8* rk = r + k * units;
+  WD_SITE_LOOP(i, V) {
+    cx<float> pv[12], rv[12];
+    load_spinor(pk, V, static_cast<int>(i), pv);
+    cg_site_update_x(xk, V, i, pv, a);
+    load_spinor(rk, V, static_cast<int>(i), rv);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) pv[c] = {fmar(b, pv[c].re, rv[c].re), fmar(b, pv[c].im, rv[c].im)};
+    store_half_site(pk, i, pv);
+  }
 }
 
 // p = r + beta p
@@ -564,6 +625,21 @@ hipError_t blas_update_p(void* p, const void* r, int prec, long n, long V, const
     update_p_half_kernel<<<grid(V, set.n), kThreads, 0, st>>>(static_cast<h8*>(p),
                                                               static_cast<const h8*>(r), n, V, set, rr,
                                                               nrr, scal);
+  return hipGetLastError();
+}
+
+hipError_t blas_update_xp_lo(void* x, void* p, const void* r, int prec, long n, long nlo32, long V,
+                             const RhsSet& set, const double* rr, int nrr, double* scal, hipStream_t st) {
+  if (prec == WD_FP32)
+    update_xp_lo_kernel<<<grid(n, set.n), kThreads, 0, st>>>(static_cast<float4*>(x), static_cast<float4*>(p),
+                                                             static_cast<const float4*>(r), n, set, rr, nrr,
+                                                             scal);
+  else if (prec == WD_FP16)
+    update_xp_half_kernel<<<grid(V, set.n), kThreads, 0, st>>>(static_cast<float4*>(x), static_cast<h8*>(p),
+                                                               static_cast<const h8*>(r), n, nlo32, V, set,
+                                                               rr, nrr, scal);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

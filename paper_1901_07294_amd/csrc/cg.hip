@@ -157,8 +157,9 @@ int CgEngine::iterate(const RhsSet& set) {
   }
   if (lay_.nslices > 0) {
     // t = Q p, with <p, A p> = |t|^2 summed per tile slice in the same launch;
-    // then Q t = A p used at once for x += alpha p, r -= alpha A p, with
-    // <r, r> per tile slice (A p is never stored); then p = r + beta p
+    // then Q t = A p used at once for r -= alpha A p, with <r, r> per tile
+    // slice (A p is never stored); then x += alpha p and p = r + beta p
+    // together (p is read once)
     CgFuse f{};
     f.mode = kCgNorm;
     f.rr = paps_;
@@ -166,20 +167,18 @@ int CgEngine::iterate(const RhsSet& set) {
     int rc = launch_status(launch_dslash_cg(glo_, m, set.n, set.idx, at(ws_, lay_.p), at(ws_, lay_.t), f,
                                             st_), "cg: Q p with |Q p|^2");
     f.mode = kCgUpdate;
-    f.x = inner_ == WD_FP64 ? x_ : at(ws_, lay_.x_lo);
-    f.xstride = inner_ == WD_FP64 ? nhi_ : n32_;
     f.r = at(ws_, lay_.r);
-    f.p = at(ws_, lay_.p);
     f.pap = paps_;
     f.npap = lay_.nslices;
     f.rr = rr_;
     f.scal = scal_;
     if (rc == WD_OK)
       rc = launch_status(launch_dslash_cg(glo_, m, set.n, set.idx, at(ws_, lay_.t), nullptr, f, st_),
-                         "cg: Q Q p with x, r");
+                         "cg: Q Q p with r");
     if (rc == WD_OK)
-      rc = launch_status(blas_update_p(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, V_, set, rr_,
-                                       lay_.nslices, scal_, st_), "cg: p");
+      rc = launch_status(blas_update_xp_lo(at(ws_, lay_.x_lo), at(ws_, lay_.p), at(ws_, lay_.r), inner_,
+                                           nlo_, n32_, V_, set, rr_, lay_.nslices, scal_, st_),
+                         "cg: x, p");
     return rc;
   }
   int rc = launch_status(launch_dslash_multi(glo_, m, set.n, set.idx, at(ws_, lay_.p),

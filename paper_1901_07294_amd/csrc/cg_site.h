@@ -1,9 +1,9 @@
-// One site's CG vector update x += alpha p, r -= alpha (A p), for the three
-// storage precisions, shared by the CG vector kernels and by the dslash
-// launch that fuses the update into its epilogue; it returns the site's
-// contribution to <r, r> (of the values as stored). Also the store of a site
-// of t = Q p with its squared norm, for the dslash launch that fuses
-// <p, A p> = |t|^2 into its epilogue.
+// One site's CG residual update r -= alpha (A p), for the dslash launch that
+// fuses it into its epilogue (FP32 and FP16 storage), and the whole vector
+// update x += alpha p, r -= alpha (A p) of FP16-storage vectors for the
+// separate kernel; each returns the site's contribution to <r, r> (of the
+// values as stored). Also the store of a site of t = Q p with its squared
+// norm, for the dslash launch that fuses <p, A p> = |t|^2 into its epilogue.
 #pragma once
 
 #include "fields.h"
@@ -45,64 +45,40 @@ __device__ __forceinline__ double store_half_site(h8* __restrict__ p, long s, co
   return n;
 }
 
-// FP64 vectors: x is the FP64 solution; ap holds A p at the site.
-__device__ __forceinline__ double cg_site_update(double2* __restrict__ x, double2* __restrict__ r,
-                                                 const double2* __restrict__ p, long V, long s,
-                                                 const cx<double> (&ap)[12], double alpha) {
-  double n = 0.0;
-#pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    const long e = pidx(s, c, 12, V);
-    double2 xe = x[e];
-    double2 re = r[e];
-    const double2 pe = p[e];
-    xe.x = fmar(alpha, pe.x, xe.x);
-    xe.y = fmar(alpha, pe.y, xe.y);
-    re.x = fmar(-alpha, ap[c].re, re.x);
-    re.y = fmar(-alpha, ap[c].im, re.y);
-    x[e] = xe;
-    r[e] = re;
-    n += norm2(re);
-  }
-  return n;
-}
-
-// FP32 vectors: x is the FP32 accumulator x_lo (same layout as r and p).
-__device__ __forceinline__ double cg_site_update(float4* __restrict__ x, float4* __restrict__ r,
-                                                 const float4* __restrict__ p, long V, long s,
-                                                 const cx<float> (&ap)[12], double alpha) {
+// r -= alpha (A p) at one site; ap holds A p. FP32 vectors.
+__device__ __forceinline__ double cg_site_update_r(float4* __restrict__ r, long V, long s,
+                                                   const cx<float> (&ap)[12], double alpha) {
   const float a = static_cast<float>(alpha);
   double n = 0.0;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     const long e = pidx(s, j, 6, V);
-    float4 xe = x[e];
     float4 re = r[e];
-    const float4 pe = p[e];
-    xe.x = fmar(a, pe.x, xe.x);
-    xe.y = fmar(a, pe.y, xe.y);
-    xe.z = fmar(a, pe.z, xe.z);
-    xe.w = fmar(a, pe.w, xe.w);
     re.x = fmar(-a, ap[2 * j].re, re.x);
     re.y = fmar(-a, ap[2 * j].im, re.y);
     re.z = fmar(-a, ap[2 * j + 1].re, re.z);
     re.w = fmar(-a, ap[2 * j + 1].im, re.w);
-    x[e] = xe;
     r[e] = re;
     n += norm2(re);
   }
   return n;
 }
 
-// FP16-storage vectors: x is the FP32 accumulator x_lo (FP32 layout); r is
-// requantised per site.
-__device__ __forceinline__ double cg_site_update(float4* __restrict__ x, h8* __restrict__ r,
-                                                 const h8* __restrict__ p, long V, long s,
-                                                 const cx<float> (&ap)[12], double alpha) {
+// The same for FP16-storage vectors: r is requantised per site.
+__device__ __forceinline__ double cg_site_update_r(h8* __restrict__ r, long V, long s,
+                                                   const cx<float> (&ap)[12], double alpha) {
   const float a = static_cast<float>(alpha);
-  cx<float> pv[12], rv[12];
-  load_spinor(p, V, static_cast<int>(s), pv);
+  cx<float> rv[12];
   load_spinor(r, V, static_cast<int>(s), rv);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) rv[c] = {fmar(-a, ap[c].re, rv[c].re), fmar(-a, ap[c].im, rv[c].im)};
+  return store_half_site(r, s, rv);
+}
+
+// x_lo += alpha p at one site, x_lo the FP32 accumulator (FP32 layout) and p
+// in FP16 storage (pv: p at the site, dequantised).
+__device__ __forceinline__ void cg_site_update_x(float4* __restrict__ x, long V, long s,
+                                                 const cx<float> (&pv)[12], float a) {
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     const long e = pidx(s, j, 6, V);
@@ -113,9 +89,18 @@ __device__ __forceinline__ double cg_site_update(float4* __restrict__ x, h8* __r
     xe.w = fmar(a, pv[2 * j + 1].im, xe.w);
     x[e] = xe;
   }
-#pragma unroll
-  for (int c = 0; c < 12; ++c) rv[c] = {fmar(-a, ap[c].re, rv[c].re), fmar(-a, ap[c].im, rv[c].im)};
-  return store_half_site(r, s, rv);
+}
+
+// FP16-storage vectors: x is the FP32 accumulator x_lo (FP32 layout); r is
+// requantised per site.
+__device__ __forceinline__ double cg_site_update(float4* __restrict__ x, h8* __restrict__ r,
+                                                 const h8* __restrict__ p, long V, long s,
+                                                 const cx<float> (&ap)[12], double alpha) {
+  const float a = static_cast<float>(alpha);
+  cx<float> pv[12];
+  load_spinor(p, V, static_cast<int>(s), pv);
+  cg_site_update_x(x, V, s, pv, a);
+  return cg_site_update_r(r, V, s, ap, alpha);
 }
 
 // Stores a site of t = Q p (streaming stores, as the plain operator) and

@@ -10,7 +10,6 @@
 // bytes per site in FP64), so there is no matrix-core work here: every lane
 // streams its site's links and spinor planes, coalesced across the wave.
 #include <atomic>
-#include <type_traits>
 
 #include "blas.h"
 #include "cg_site.h"
@@ -287,7 +286,6 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
   // its lanes (an order fixed by the tile size, which the lattice fixes);
   // after the prologue's barrier every lane adds the wave sums in order, so
   // all lanes of all workgroups get the same alpha
-  using XV = typename std::conditional<sizeof(R) == 8, double2, float4>::type;
   double* cgs = reinterpret_cast<double*>(reinterpret_cast<SV*>(smem) + p.gw * 2 * RB * kPlanes * n) +
                 slot * RB * kCgLds;
   double alpha[RB];
@@ -395,10 +393,7 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
       epilogue(psi, acc[r], diag[r], gamma5, o);
       if constexpr (CGM == kCgUpdate) {
         const long k = diags.idx[rhs0 + r];
-        double v = cg_site_update(static_cast<XV*>(cgf.x) + k * cgf.xstride,
-                                  const_cast<GS*>(reinterpret_cast<const GS*>(cgf.r)) + k * stride,
-                                  reinterpret_cast<const GS*>(cgf.p) + k * stride, V, st, o,
-                                  alpha[r]);
+        double v = cg_site_update_r(static_cast<GS*>(cgf.r) + k * stride, V, st, o, alpha[r]);
         v = wave_total(v);
         if ((tid & 63) == 0) cgs[r * kCgLds + 4 * ((t - t0) & 1) + (tid >> 6)] = v;
       } else if constexpr (CGM == kCgNorm) {

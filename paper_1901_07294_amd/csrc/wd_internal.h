@@ -106,20 +106,18 @@ bool tuned_lookup(const int32_t dims[4], int prec, int c12, int nrhs, MarchTunin
 // and each tile slice (a tile's x rows at one z and t, so the grouping is
 // fixed by the lattice, not the launch) leaves its |t|^2 = <p, A p> partial
 // sum in rr. kCgUpdate (second application, A p = Q t): A p is used at once
-// for x += alpha p and r -= alpha A p (alpha = <r,r> / <p,Ap> reduced from
-// pap) instead of being stored, and each tile slice leaves its <r,r>.
+// for r -= alpha A p (alpha = <r,r> / <p,Ap> reduced from pap) instead of
+// being stored, and each tile slice leaves its <r,r>; x += alpha p is left
+// to the p update, which reads p anyway.
 enum : int { kCgNone = 0, kCgNorm = 1, kCgUpdate = 2 };
 struct CgFuse {
   int mode;           // kCgNorm or kCgUpdate
-  void* x;            // FP64 solution (FP64 vectors) or FP32 accumulator x_lo
   void* r;            // residual, inner precision
-  const void* p;      // search direction, inner precision
   const double* pap;  // <p, A p> partial sums, npap per field slot
   int npap;
   double* rr;         // out: |t|^2 or <r, r> per tile slice, nslices per field slot
   int nslices;
   double* scal;       // per field slot scalars (kScalars doubles)
-  long xstride;       // 16-byte elements of x per field slot
 };
 // Tile slices of the fused work on a lattice in a precision, or 0 where it
 // does not apply (the one-site-per-lane kernel, or tiles that are not whole
