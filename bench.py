@@ -45,24 +45,52 @@ def compulsory_bytes(prec: str, c12: bool) -> int:
 # timed, else null.
 TRAFFIC = {
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated KiB per dispatch), measured for
-    # the kernel sources hashed below, per launch "tb,gw,group,rb" the bytes belong to
-    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "5bb31f3eca42aa0b", "launches": {
-        "32,1,32,1": 2248531296,    # 901,307.7 / 393,216.0
-        "16,1,64,1": 2376253760}},  # 963,672.2 / 393,216.0
-    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "5bb31f3eca42aa0b", "launches": {
-        "16,1,64,1": 1123991360}},  # 450,519.9 / 196,608.0
-    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "5bb31f3eca42aa0b", "launches": {
-        "4,1,256,1": 622346976}},   # 250,632.4 / 106,496.0
+    # the kernel code hashed below, per launch "tb,gw,group,rb" the bytes belong to
+    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "40357ec387863f3b", "launches": {
+        "32,1,32,1": 2260103712,    # 906,958.3 / 393,216.0
+        "16,1,64,1": 2379502656}},  # 965,258.5 / 393,216.0
+    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "40357ec387863f3b", "launches": {
+        "16,1,64,1": 1123403296}},  # 450,232.8 / 196,608.0
+    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "40357ec387863f3b", "launches": {
+        "4,1,256,1": 622496448}},   # 250,705.3 / 106,496.0
 }
 KERNEL_SOURCES = ["paper_1901_07294_amd/csrc/dslash.hip", "paper_1901_07294_amd/csrc/stencil.h",
                   "paper_1901_07294_amd/csrc/fields.h", "paper_1901_07294_amd/csrc/cplx.h"]
 
 
+def strip_comments(src: str) -> str:
+    """C++ source text without its comments (string and character literals
+    kept), trailing blanks and empty lines: the code a compiler sees."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    lines = (ln.rstrip() for ln in "".join(out).splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_source_hash() -> str:
+    """Hash of the dslash kernels' code (comments excluded, so that editing
+    one does not orphan counters taken on the same code)."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            h.update(strip_comments(f.read()).encode())
     return h.hexdigest()[:16]
 
 

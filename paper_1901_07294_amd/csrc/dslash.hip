@@ -205,14 +205,15 @@ constexpr int kCgLds = 2 * 4 + 4;
 // arithmetic precision (FP32 for FP16 storage).
 // CGM (CG iterations, n a multiple of 64): kCgNorm stores the output and
 // leaves each tile slice's squared norm of it in cgf.rr; kCgUpdate does not
-// store the output but applies the CG update of cgf to the field slots.
-// Three waves per SIMD (the plain FP32-arithmetic kernel's occupancy) are
-// kept, at the cost of a few spilled registers, where that was measured to
-// pay: Q p with its norm in FP32 storage, and the update in FP16 storage.
+// store the output but applies r -= alpha A p of cgf to the field slots (x
+// and p follow in a separate kernel).
+// The fused modes with FP32 arithmetic and one right-hand side per lane are
+// compiled for three waves per SIMD (the plain FP32-arithmetic kernel's
+// occupancy), at the cost of a few spilled registers in FP32 storage, which
+// measured faster than two waves without spills.
 template <int CGM, typename T, int RB>
 constexpr int march_waves_per_eu() {
-  return RB == 1 && ((CGM == kCgNorm && sizeof(T) == 4) || (CGM == kCgUpdate && sizeof(T) == 2)) ? 3
-                                                                                                : 1;
+  return RB == 1 && sizeof(typename Packed<T>::R) == 4 && CGM != kCgNone ? 3 : 1;
 }
 
 template <typename T, bool C12, int MAXT, int RB, int CGM>

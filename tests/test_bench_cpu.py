@@ -34,3 +34,19 @@ def test_traffic_table_entries_name_launches_and_byte_counts():
     v = 32 * 32 * 32 * 64
     for nbytes in bench.TRAFFIC["wilson_dslash_32x32x32x64_fp64"]["launches"].values():
         assert nbytes >= 960 * v
+
+
+def test_source_hash_ignores_comments_but_not_code():
+    src = ('int a = 1; // note "x"\n'
+           '/* block\n   comment */ int b = \'/\';\n'
+           'const char* s = "// kept \\" /* kept */";\n'
+           '\n'
+           'int c;   \n')
+    stripped = bench.strip_comments(src)
+    assert stripped == ('int a = 1;\n'
+                        '  int b = \'/\';\n'
+                        'const char* s = "// kept \\" /* kept */";\n'
+                        'int c;')
+    # a comment edit (even one that adds lines) leaves the code, a code edit does not
+    assert bench.strip_comments(src.replace("// note", "// another\n// note")) == stripped
+    assert bench.strip_comments(src.replace("int c;", "int d;")) != stripped
