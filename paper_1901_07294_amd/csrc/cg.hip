@@ -186,12 +186,12 @@ int CgEngine::iterate(const RhsSet& set) {
   if (rc == WD_OK)
     rc = launch_status(launch_dslash_multi(glo_, m, set.n, set.idx, at(ws_, lay_.t),
                                            at(ws_, lay_.ap), WD_FLAG_GAMMA5, st_), "cg: Q Q p");
-  // <p, A p> = |Q p|^2: partial sums here, reduced (with alpha) inside the x, r update
+  // <p, A p> = |Q p|^2: partial sums here, reduced (with alpha) inside the r update
   int npap = 0;
   if (rc == WD_OK)
     rc = launch_status(blas_norm2_partials(at(ws_, lay_.t), inner_, nlo_, V_, set, pap_, &npap, st_),
                        "cg: pAp");
-  // <r, r> likewise: partial sums in the x, r update, reduced (with beta) inside the p update
+  // <r, r> likewise: partial sums in the r update, reduced (with beta) inside the p update
   int nrr = 0;
   if (inner_ == WD_FP64) {  // r first, then x and p together (p read once)
     if (rc == WD_OK)
