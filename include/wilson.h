@@ -260,7 +260,12 @@ WD_API size_t cg_workspace_bytes(const int32_t dims[4], int32_t nrhs, int32_t in
  * cg_workspace_bytes(...) bytes of caller-owned device memory, not
  * overlapping b_dev or x_dev. stats_host: nrhs entries (may be NULL).
  * Synchronous: work is enqueued on stream and the call returns when every
- * right-hand side has converged, failed or used max_iter iterations.
+ * right-hand side has converged, failed or used max_iter iterations. Every
+ * check_every iterations the calling thread reads the scalars back and waits
+ * for them by polling the stream (a busy wait; with use_graph, a blocking
+ * wait); they land in a page-locked host buffer of 1,280 bytes that the
+ * library takes from a pool of its own, one per call in progress, and keeps
+ * for reuse until the process ends.
  * Returns WD_OK if all converged, else WD_ERR_NOT_CONVERGED or
  * WD_ERR_NUMERIC (per right-hand side detail in stats_host), or an argument
  * or device error. */
