@@ -26,6 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "dslash GFlop/s & % HBM peak; mixed-prec CG solves/s, p50/p99 latency"
 FLOPS_PER_SITE = 1320
 HBM_PEAK_GBS = 8000.0
+# FP32 vector rate without packed FP32 instructions, which the build disables
+# (157.3 TFLOP/s with them); the arithmetic of the FP32 and FP16-storage paths
+FP32_VECTOR_PEAK_GFLOPS = 78600.0
 DIMS = (32, 32, 32, 64)
 CONFIG_INDEX = 2          # seeds of the production-lattice configuration
 
@@ -237,6 +240,15 @@ def bench_latency(torch, w, li, DeviceGauge, oracle, n=1000):
             "parity_ok": err <= 1e-13}
 
 
+def multi_roof(nrhs: int, bytes_per_site: int, gflops: float) -> dict:
+    """The roof of a fused multi-right-hand-side launch: the smaller of the HBM
+    peak times its arithmetic intensity (nrhs x 1320 flop per bytes_per_site)
+    and the FP32 vector peak, and the fraction of it that gflops reaches."""
+    by_hbm = HBM_PEAK_GBS * nrhs * FLOPS_PER_SITE / bytes_per_site
+    bound, roof = ("alu", FP32_VECTOR_PEAK_GFLOPS) if FP32_VECTOR_PEAK_GFLOPS < by_hbm else ("hbm", by_hbm)
+    return {"bound": bound, "roof_gflops": round(roof, 1), "frac": round(gflops / roof, 4)}
+
+
 def bench_multi(torch, w, li, DeviceGauge, prec="fp32", steps=50, warmup=5, inputs=None):
     """12 right-hand sides on 24^3 x 48, near-unity links, FP32 or FP16 storage:
     one fused launch against 12 single launches."""
@@ -280,11 +292,13 @@ def bench_multi(torch, w, li, DeviceGauge, prec="fp32", steps=50, warmup=5, inpu
         ref = oracle.dslash_sites(U, psis[k], masses[k], sites)
         err = max(err, float(np.linalg.norm(outs[k][sites] - ref) / np.linalg.norm(ref)))
     tol = {"fp32": 1e-6, "fp16": 2e-3}[prec]
+    gflops = nrhs * FLOPS_PER_SITE * V / (fused / 1e3) / 1e9
     return {"workload": "wilson_dslash_multi_24x24x24x48_x12", "prec": prec, "links": "full",
             "parity": {"max_rel_err": err, "tol": tol, "sites_per_field": 256, "ok": err <= tol},
             "gauge": "near-unity eps=0.3", "ms_per_apply": round(fused, 4),
-            "gflops": round(nrhs * FLOPS_PER_SITE * V / (fused / 1e3) / 1e9, 1),
+            "gflops": round(gflops, 1),
             "pct_hbm_peak": round(100 * comp * V / (fused / 1e3) / 1e9 / HBM_PEAK_GBS, 2),
+            "roof": multi_roof(nrhs, comp, gflops),
             "ms_12_single_applies": round(single, 4), "speedup_vs_single": round(single / fused, 3),
             "tuning": tuned}
 

@@ -50,3 +50,15 @@ def test_source_hash_ignores_comments_but_not_code():
     # a comment edit (even one that adds lines) leaves the code, a code edit does not
     assert bench.strip_comments(src.replace("// note", "// another\n// note")) == stripped
     assert bench.strip_comments(src.replace("int c;", "int d;")) != stripped
+
+
+def test_multi_rhs_roof_is_the_smaller_of_hbm_and_alu():
+    # FP32, 12 fields: links once (288 B) + 12 x (in + out) (96 B each) = 2592 B per site;
+    # 8 TB/s x 12 x 1320 / 2592 = 48.9 TFLOP/s, below the 78.6 TFLOP/s vector peak
+    r = bench.multi_roof(12, 2592, 19201.7)
+    assert r["bound"] == "hbm" and abs(r["roof_gflops"] - 8000 * 12 * 1320 / 2592) < 0.1
+    assert abs(r["frac"] - 19201.7 / (8000 * 12 * 1320 / 2592)) < 1e-4
+    # FP16 storage: 144 + 12 x 2 x 52 = 1392 B per site would allow 91 TFLOP/s: ALU-bound
+    r = bench.multi_roof(12, 1392, 26032.7)
+    assert r["bound"] == "alu" and r["roof_gflops"] == bench.FP32_VECTOR_PEAK_GFLOPS
+    assert abs(r["frac"] - 26032.7 / 78600.0) < 1e-4
