@@ -183,11 +183,26 @@ __device__ __forceinline__ _Float16 f32_to_half(float x) {
 }
 
 // Quantises a site: scale = max |component|, q = v * (1 / scale) rounded to
-// FP32 and then to binary16.
+// FP32 and then to binary16. When the scale is subnormal (below 2^-126) its
+// reciprocal would overflow to infinity; such a site is first multiplied by
+// 2^64 (exact), which gives the same q as unbounded exponents would, and the
+// stored scale stays the site's own largest modulus.
 __device__ __forceinline__ float half_quantise(const cx<float> (&v)[12], h8 (&q)[3]) {
   float m = 0.0f;
 #pragma unroll
   for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+  if (m > 0.0f && m < 0x1p-126f) {
+    const float k = 0x1p64f;
+    const float inv = 1.0f / (m * k);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        q[j][2 * c] = f32_to_half((v[4 * j + c].re * k) * inv);
+        q[j][2 * c + 1] = f32_to_half((v[4 * j + c].im * k) * inv);
+      }
+    return m;
+  }
   const float inv = m > 0.0f ? 1.0f / m : 0.0f;
 #pragma unroll
   for (int j = 0; j < 3; ++j)

@@ -203,7 +203,10 @@ Group* wd_server::make_group(GaugeEntry* ge, int need) {
   g->eng = std::make_unique<CgEngine>(ge->hi, cfg.inner != WD_FP64 ? ge->lo : ge->hi, cfg.inner, S, b,
                                       x, ws, g->stream);
   g->slots.assign(S, Slot{});
-  ge->groups++;
+  {
+    std::lock_guard<std::mutex> lk(mu);  // eviction reads the count under the lock
+    ge->groups++;
+  }
   groups.push_back(std::move(g));
   return groups.back().get();
 }
@@ -213,9 +216,9 @@ void wd_server::destroy_group(size_t i) {
   (void)hipStreamSynchronize(g.stream);
   (void)hipEventDestroy(g.ev);
   (void)hipHostFree(g.host_scal);
-  g.gauge->groups--;
   {
     std::lock_guard<std::mutex> lk(mu);
+    g.gauge->groups--;
     arena.release(g.mem);
   }
   groups.erase(groups.begin() + static_cast<long>(i));
@@ -561,13 +564,27 @@ int cg_submit(wd_server* s, const wd_request* req, uint64_t* ticket) {
       return set_error(WD_ERR_INVALID_ARG, "need tol > 0 and max_iter >= 1");
     for (int k = 0; k < req->nrhs; ++k)
       if (!std::isfinite(req->masses[k])) return set_error(WD_ERR_INVALID_ARG, "mass %d is not finite", k);
+    // Reserve the gauge field before the lock is dropped: with requests > 0 no
+    // eviction and no removal frees it. Every error return below gives the
+    // reservation back under the lock (a removed field is then freed by the
+    // scheduler as usual).
+    ge->requests++;
+    int32_t gdims[4];
+    for (int i = 0; i < 4; ++i) gdims[i] = ge->dims[i];
+    const long gV = ge->V;
     lk.unlock();
-    const size_t vec = static_cast<size_t>(packed_sites(ge->V)) * req->nrhs * spinor_site_bytes(WD_FP64);
+    auto unreserve = [&](int code) {
+      lk.lock();
+      ge->requests--;
+      s->cv.notify_all();
+      return code;
+    };
+    const size_t vec = static_cast<size_t>(packed_sites(gV)) * req->nrhs * spinor_site_bytes(WD_FP64);
     int rc = check_device_range(req->b_dev, vec, "b_dev");
     if (rc == WD_OK) rc = check_device_range(req->x_dev, vec, "x_dev");
-    if (rc != WD_OK) return rc;
+    if (rc != WD_OK) return unreserve(rc);
     if (overlaps(req->b_dev, vec, req->x_dev, vec))
-      return set_error(WD_ERR_INVALID_ARG, "b_dev and x_dev overlap");
+      return unreserve(set_error(WD_ERR_INVALID_ARG, "b_dev and x_dev overlap"));
     {
       // the arena minus the registered gauge fields must hold a group of the
       // request's right-hand sides
@@ -577,8 +594,9 @@ int cg_submit(wd_server* s, const wd_request* req, uint64_t* ticket) {
         if (!g->removing)
           gauges += align256(wd_gauge_bytes(g->dims, WD_FP64, 0)) + inner_gauge_bytes(g->dims, s->cfg.inner);
       lk.unlock();
-      if (group_bytes(ge->dims, ge->V, req->nrhs, s->cfg.inner) + gauges > s->cfg.arena_bytes)
-        return set_error(WD_ERR_NOMEM, "a solve group of this lattice cannot fit beside the gauge fields");
+      if (group_bytes(gdims, gV, req->nrhs, s->cfg.inner) + gauges > s->cfg.arena_bytes)
+        return unreserve(
+            set_error(WD_ERR_NOMEM, "a solve group of this lattice cannot fit beside the gauge fields"));
     }
     auto rq = std::make_unique<Request>();
     rq->r = *req;
@@ -586,11 +604,13 @@ int cg_submit(wd_server* s, const wd_request* req, uint64_t* ticket) {
     rq->remaining = req->nrhs;
     for (int k = 0; k < req->nrhs; ++k) rq->stats[k].status = WD_PENDING;
     lk.lock();
-    if (s->stop) return set_error(WD_ERR_CANCELLED, "server is shutting down");
+    if (s->stop) {
+      ge->requests--;
+      return set_error(WD_ERR_CANCELLED, "server is shutting down");
+    }
     rq->t_submit = s->now();
     rq->ticket = s->next_ticket++;
     *ticket = rq->ticket;
-    ge->requests++;
     ge->last_used = s->now();
     s->running.fetch_add(1);
     s->submitted.push_back(rq.get());

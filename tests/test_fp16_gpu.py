@@ -56,9 +56,12 @@ def half_spinor(psi):
     v = np.stack([psi.real, psi.imag], -1).astype(np.float32)
     flat = v.reshape(v.shape[:-3] + (24,))
     m = np.abs(flat).max(-1, keepdims=True)
+    # a subnormal site scale is handled with both operands times 2^64 (exact), so
+    # its reciprocal does not overflow: the q of unbounded exponents
+    k = np.where((m > 0) & (m < np.float32(2.0 ** -126)), np.float32(2.0 ** 64), np.float32(1.0))
     inv = np.zeros_like(m)
-    np.divide(np.float32(1.0), m, out=inv, where=m > 0)
-    q = (flat * inv).astype(np.float16)
+    np.divide(np.float32(1.0), m * k, out=inv, where=m > 0)
+    q = ((flat * k) * inv).astype(np.float16)
     deq = (q.astype(np.float32) * m).astype(np.float64).reshape(v.shape)
     return deq[..., 0] + 1j * deq[..., 1]
 
@@ -92,6 +95,33 @@ def test_fp16_pack_matches_format():
     assert np.all(back[0, 0, 0, 0, 1] == 0)
     # the format rounds each component to within half a step of its site scale
     check_rounding_bound(back, psi, arith=0.0)
+
+
+def test_fp16_subnormal_site_scale():
+    """A site whose largest component is FP32-subnormal (below 2^-126): its
+    reciprocal scale would overflow, so the format scales it by 2^64 first. The
+    stored site, the operator's output next to it and a field that is zero
+    except for that site must all stay finite and match the oracle."""
+    dims = (16, 8, 4, 4)  # t-marching tiles
+    U = li.random_gauge(dims, 391)
+    psi = li.gaussian_spinor(dims, 392)
+    tiny = 1e-39 * li.gaussian_spinor(dims, 393)[1, 2, 3, 4]
+    assert np.abs(np.stack([tiny.real, tiny.imag])).max() < 2.0 ** -126
+    psi[1, 2, 3, 4] = tiny
+    alone = np.zeros_like(psi)
+    alone[1, 2, 3, 4] = tiny
+    g = DeviceGauge(U, w.WD_FP16)
+    for field in (psi, alone):
+        src = g.pack(field)
+        back = g.unpack(src)
+        assert np.all(np.isfinite(back))
+        assert np.array_equal(back, half_spinor(field))
+        assert rel(back[1, 2, 3, 4], tiny) < 1e-3
+        dst = g.spinor()
+        w.dslash_apply(g.handle, 0.1, src, dst, w.WD_FP16)
+        out = g.unpack(dst)
+        assert np.all(np.isfinite(out))
+        assert rel(out, oracle.dslash(U, field, 0.1)) <= TOL[w.WD_FP16]
 
 
 SHAPES = [
