@@ -115,6 +115,8 @@ def parse(argv=None):
                     help="skip the secondary precision/compression measurements")
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-RHS measurement")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG solves/s measurement")
+    ap.add_argument("--no-cg-multi", action="store_true", help="skip the 12-RHS CG measurement")
+    ap.add_argument("--no-wilson", action="store_true", help="skip the D x = b (even-odd) measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch choices (skip the autotuner)")
@@ -397,6 +399,110 @@ def bench_cg(torch, w, li, DeviceGauge, reps=5, cpu=True):
     return out
 
 
+def bench_cg_multi(torch, w, li, DeviceGauge, nrhs=12, reps=3, single_fp64_ms=None):
+    """One cg_solve_normal call on 12 right-hand sides of 24^4 (m = 0.05,
+    near-unity links, tol 1e-10): plain FP64 CG against FP32 and FP16-storage
+    inner iterations with FP64 reliable updates, in right-hand-side solves per
+    second, and against 12 separate single-right-hand-side FP64 solves. The
+    oracle recomputes |b - D^dag D x| / |b| of the first and last right-hand
+    side of every batch outside the timed region."""
+    import oracle
+    dims, m = (24, 24, 24, 24), 0.05
+    U = li.near_unity_gauge(dims, li.seed_gauge(4), 0.3)
+    bs = li.gaussian_spinors(dims, [li.seed_spinor(4, k) for k in range(nrhs)])
+    ghi = DeviceGauge(U, w.WD_FP64)
+    glo = {w.WD_FP64: ghi, w.WD_FP32: DeviceGauge(U, w.WD_FP32), w.WD_FP16: DeviceGauge(U, w.WD_FP16)}
+    b = ghi.pack(bs, nrhs=nrhs)
+    x = ghi.spinor(nrhs)
+    out = {"workload": f"cg_normal_24x24x24x24_m0.05_x{nrhs}", "tol": 1e-10, "nrhs": nrhs,
+           "gauge": "near-unity eps=0.3", "check_every": 8}
+    for name, inner in (("fp64", w.WD_FP64), ("mixed_fp32", w.WD_FP32), ("mixed_fp16", w.WD_FP16)):
+        for g in {id(ghi): ghi, id(glo[inner]): glo[inner]}.values():
+            tune(torch, w, g, nrhs, g.pack(bs, nrhs=nrhs))
+        ws = torch.empty(w.cg_workspace_bytes(dims, nrhs, inner), dtype=torch.uint8, device="cuda")
+        params = dict(tol=1e-10, max_iter=20000, inner=inner, delta=0.1, check_every=8, x0_given=0,
+                      use_graph=0)
+        gl = glo[inner].handle
+        w.cg_solve_normal(ghi.handle, gl, [m] * nrhs, nrhs, b, x, params, ws)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rc, st = w.cg_solve_normal(ghi.handle, gl, [m] * nrhs, nrhs, b, x, params, ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        xs = ghi.unpack(x, nrhs=nrhs)
+        res = []
+        for k in (0, nrhs - 1):
+            r = bs[k] - oracle.normal_op(U, m, xs[k])
+            res.append(float(np.linalg.norm(r) / np.linalg.norm(bs[k])))
+        out[name] = {"status": rc, "ms_per_batch": round(dt * 1e3, 2),
+                     "rhs_solves_per_s": round(nrhs / dt, 2),
+                     "iters_max": max(s["iters"] for s in st),
+                     "reliable_updates_max": max(s["reliable_updates"] for s in st),
+                     "true_rel_residual_max": max(s["true_rel_residual"] for s in st),
+                     "oracle_true_rel_residual_sample": res}
+        del ws
+        print(f"[bench] cg x{nrhs} {name}: {out[name]['rhs_solves_per_s']} RHS solves/s",
+              file=sys.stderr, flush=True)
+    base = out["fp64"]["rhs_solves_per_s"]
+    for name in ("mixed_fp32", "mixed_fp16"):
+        out[name]["speedup_vs_fp64_batch"] = round(out[name]["rhs_solves_per_s"] / base, 3)
+    if single_fp64_ms:
+        out["single_fp64_rhs_solves_per_s"] = round(1e3 / single_fp64_ms, 2)
+        for name in ("fp64", "mixed_fp32", "mixed_fp16"):
+            out[name]["speedup_vs_single_fp64"] = round(out[name]["rhs_solves_per_s"] * single_fp64_ms / 1e3, 3)
+    return out
+
+
+def bench_wilson(torch, w, li, DeviceGauge, reps=3):
+    """Solves of D x = b itself on 24^4 (m = 0.05, near-unity links) to
+    |b - D x| / |b| <= 1e-10: the normal equations D^dag D x = D^dag b against
+    even-odd preconditioning (CG on the odd-site Schur complement), FP64 and
+    FP16-storage inner iterations. The oracle recomputes |b - D x| / |b| of
+    every solution outside the timed region."""
+    import oracle.solve_ref as sr
+    dims, m = (24, 24, 24, 24), 0.05
+    U = li.near_unity_gauge(dims, li.seed_gauge(4), 0.3)
+    bh = li.gaussian_spinor(dims, li.seed_spinor(4))
+    out = {"workload": "wilson_solve_24x24x24x24_m0.05", "tol": 1e-10, "gauge": "near-unity eps=0.3",
+           "check_every": 8}
+    for eo in (False, True):
+        ghi = DeviceGauge(U, w.WD_FP64, eo=eo)
+        b = ghi.pack(bh)
+        x = ghi.spinor()
+        for iname, inner in (("fp64", w.WD_FP64), ("mixed_fp16", w.WD_FP16)):
+            glo = DeviceGauge(U, inner, eo=eo) if inner != w.WD_FP64 else ghi
+            if not eo:
+                for g in {id(ghi): ghi, id(glo): glo}.values():
+                    tune(torch, w, g, 1, g.pack(bh))
+            ws = torch.empty(w.wilson_workspace_bytes(dims, 1, inner, eo), dtype=torch.uint8,
+                             device="cuda")
+            params = dict(tol=1e-10, max_iter=20000, inner=inner, delta=0.1, check_every=8,
+                          x0_given=0, use_graph=0)
+            w.cg_solve_wilson(ghi.handle, glo.handle, [m], 1, b, x, params, ws)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                rc, st = w.cg_solve_wilson(ghi.handle, glo.handle, [m], 1, b, x, params, ws)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            res = sr.wilson_residual(U, m, bh, ghi.unpack(x))
+            name = f"{'eo' if eo else 'normal'}_{iname}"
+            out[name] = {"status": rc, "solves_per_s": round(1.0 / dt, 2), "ms_per_solve": round(dt * 1e3, 3),
+                         "iters": st[0]["iters"], "reliable_updates": st[0]["reliable_updates"],
+                         "true_rel_residual": st[0]["true_rel_residual"],
+                         "oracle_wilson_rel_residual": res}
+            print(f"[bench] wilson {name}: {out[name]['solves_per_s']} solves/s, "
+                  f"{st[0]['iters']} iterations", file=sys.stderr, flush=True)
+            del ws
+    for iname in ("fp64", "mixed_fp16"):
+        out[f"eo_{iname}"]["speedup_vs_normal"] = round(
+            out[f"normal_{iname}"]["ms_per_solve"] / out[f"eo_{iname}"]["ms_per_solve"], 3)
+    out["eo_mixed_fp16"]["speedup_vs_normal_fp64"] = round(
+        out["normal_fp64"]["ms_per_solve"] / out["eo_mixed_fp16"]["ms_per_solve"], 3)
+    return out
+
+
 def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), seed=5000, arena_gib=128):
     """Request server under Poisson streams of CG solves (tol 1e-10, FP16-storage
     inner iterations with FP64 reliable updates) on a resident pool of two
@@ -670,6 +776,15 @@ def main(argv=None):
     if not args.no_cg:
         print("[bench] CG 24^4", file=sys.stderr, flush=True)
         cg = bench_cg(torch, w, li, DeviceGauge, cpu=not args.no_cpu_baseline)
+    cg_multi = None
+    if not args.no_cg_multi:
+        print("[bench] CG 24^4 x12", file=sys.stderr, flush=True)
+        cg_multi = bench_cg_multi(torch, w, li, DeviceGauge,
+                                  single_fp64_ms=cg["fp64"]["ms_per_solve"] if cg else None)
+    wilson = None
+    if not args.no_wilson:
+        print("[bench] D x = b 24^4, normal equations and even-odd", file=sys.stderr, flush=True)
+        wilson = bench_wilson(torch, w, li, DeviceGauge)
     print("[bench] latency 4^4", file=sys.stderr, flush=True)
     latency = bench_latency(torch, w, li, DeviceGauge, oracle)
 
@@ -728,6 +843,8 @@ def main(argv=None):
         "latency_4x4x4x4": latency,
         "multi_rhs": multi,
         "cg": cg,
+        "cg_multi_rhs": cg_multi,
+        "wilson_solve": wilson,
         "serve": serve,
         "kernel_source_sha": kernel_source_hash(),
         "cpu_baseline": cpu,

@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define WD_ABI_VERSION 3
+#define WD_ABI_VERSION 4
 
 #if defined(__GNUC__)
 #define WD_API __attribute__((visibility("default")))
@@ -270,6 +270,93 @@ WD_API size_t cg_workspace_bytes(const int32_t dims[4], int32_t nrhs, int32_t in
  * WD_ERR_NUMERIC (per right-hand side detail in stats_host), or an argument
  * or device error. */
 WD_API int cg_solve_normal(const wd_gauge* g_hi, const wd_gauge* g_lo, const double* masses_host,
+                           int32_t nrhs, const void* b_dev, void* x_dev,
+                           const wd_cg_params* params, wd_cg_stats* stats_host, void* ws_dev,
+                           size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Solving the Wilson system D x = b, and its even-odd (red-black) form.
+ *
+ * Sec. II-A of the paper says that iterative solvers such as conjugate
+ * gradient, dominated by applications of the Dirac operator of eq. (1), take
+ * most of a lattice QCD run; the system they solve is D x = b. On a lattice
+ * whose four extents are all even, every hop of D joins sites of opposite
+ * parity (x+y+z+t even or odd), so in the (even, odd) block order
+ *   D = [[A, -H_eo/2], [-H_oe/2, A]],   A = 4 + m,
+ * with H_pq the hopping term of eq. (1)'s operator from sites of parity q to
+ * sites of parity p. Eliminating the even sites leaves the odd-site Schur
+ * complement
+ *   S = A - H_oe H_eo / (4 A),
+ * and S x_o = b_o + H_oe b_e / (2A), x_e = (b_e + H_eo x_o / 2) / A solve
+ * D x = b. S is gamma5-Hermitian and better conditioned than D.
+ *
+ * Even-odd fields: an even-odd gauge handle (wd_gauge_import_eo) stores the
+ * links of the even sites, then those of the odd sites, each as a packed field
+ * of V/2 sites; a half spinor field holds the sites of one parity (packed, V/2
+ * sites per field, wd_spinor_eo_bytes). An even-odd handle also serves
+ * wd_spinor_import / wd_spinor_export of full-lattice spinors (they use its
+ * lattice only); dslash_apply, dslash_apply_multi, wd_tune_dslash and
+ * cg_solve_normal need a full-lattice handle (WD_ERR_INVALID_ARG otherwise).
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of an even-odd packed gauge buffer; 0 for invalid arguments or an odd
+ * extent. */
+WD_API size_t wd_gauge_eo_bytes(const int32_t dims[4], int32_t prec, int32_t compress12);
+
+/* Bytes of nrhs half spinor fields (one parity, V/2 sites each); 0 for invalid
+ * arguments or an odd extent. */
+WD_API size_t wd_spinor_eo_bytes(const int32_t dims[4], int32_t prec, int32_t nrhs);
+
+/* As wd_gauge_import, into the even-odd layout (dst_bytes >=
+ * wd_gauge_eo_bytes). Every extent must be even (WD_ERR_SHAPE otherwise). */
+WD_API int wd_gauge_import_eo(const int32_t dims[4], const void* U_canon_dev, int32_t prec,
+                              int32_t compress12, void* dst_dev, size_t dst_bytes,
+                              hipStream_t stream, wd_gauge** out);
+
+/* Packs the sites of parity `parity` (0 even, 1 odd) of nrhs canonical
+ * complex128 spinors into half spinor fields (wd_spinor_eo_bytes bytes),
+ * precision prec = g's. Enqueued on stream. g: any handle of the lattice. */
+WD_API int wd_spinor_import_eo(const wd_gauge* g, const void* canon_dev, int32_t prec, int32_t nrhs,
+                               int32_t parity, void* dst_dev, hipStream_t stream);
+
+/* Inverse of wd_spinor_import_eo: writes the half fields into the sites of
+ * parity `parity` of nrhs canonical complex128 spinors and zero into the sites
+ * of the other parity. Enqueued on stream. */
+WD_API int wd_spinor_export_eo(const wd_gauge* g, const void* src_dev, int32_t prec, int32_t nrhs,
+                               int32_t parity, void* canon_dev, hipStream_t stream);
+
+/* out_k = S(masses_host[k]) in_k, or gamma5 S in_k with WD_FLAG_GAMMA5, for the
+ * nrhs (0..16) odd half fields of in_dev; g an even-odd handle, prec = g's.
+ * tmp_dev (nrhs half fields, overwritten) receives -H_eo in / 2 on the way.
+ * in_dev, out_dev and tmp_dev must not overlap; masses must not be -4.
+ * Asynchronous on stream. Errors as dslash_apply_multi. */
+WD_API int dslash_apply_eo(const wd_gauge* g, const double* masses_host, int32_t nrhs,
+                           const void* in_dev, void* out_dev, void* tmp_dev, int32_t prec,
+                           int32_t flags, hipStream_t stream);
+
+/* Bytes of device workspace cg_solve_wilson needs for nrhs (1..16)
+ * right-hand sides, inner precision `inner`, and eo != 0 for even-odd gauge
+ * handles; 0 for invalid arguments. */
+WD_API size_t wilson_workspace_bytes(const int32_t dims[4], int32_t nrhs, int32_t inner, int32_t eo);
+
+/* Solves D(m_k) x_k = b_k for k < nrhs, each with its own mass. b_dev and x_dev
+ * hold nrhs full-lattice packed FP64 spinors (wd_spinor_bytes(dims, WD_FP64,
+ * nrhs) bytes each; x_dev is the output, and the start vector if
+ * params->x0_given). With full-lattice handles, CG solves the normal equations
+ * D^dag D x = D^dag b (D^dag b = gamma5 D gamma5 b, formed on the device); with
+ * even-odd handles (g_hi, and g_lo in the inner precision when params->inner
+ * is WD_FP32 or WD_FP16), it solves S^dag S x_o = S^dag (b_o + H_oe b_e / (2A))
+ * on the odd sites and rebuilds the even ones. Inner precision, reliable
+ * updates, delta, check_every and use_graph as cg_solve_normal.
+ * The call ends on the FP64 residual of the system itself: params->tol bounds
+ * |b_k - D x_k| / |b_k|; CG first runs to tol on its own residual and resumes
+ * with a tighter one where the system's residual is still above tol (at most
+ * 6 runs, max_iter iterations in all). stats_host[k]: iterations and reliable
+ * updates over all runs; true_rel_residual = |b_k - D x_k| / |b_k|.
+ * ws_dev: wilson_workspace_bytes(...) bytes, not overlapping b_dev or x_dev.
+ * Synchronous. Returns WD_OK if every right-hand side reached tol, else
+ * WD_ERR_NOT_CONVERGED or WD_ERR_NUMERIC, or an argument or device error. */
+WD_API int cg_solve_wilson(const wd_gauge* g_hi, const wd_gauge* g_lo, const double* masses_host,
                            int32_t nrhs, const void* b_dev, void* x_dev,
                            const wd_cg_params* params, wd_cg_stats* stats_host, void* ws_dev,
                            size_t ws_bytes, hipStream_t stream);

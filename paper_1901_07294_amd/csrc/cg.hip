@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "cg_engine.h"
+#include "eo.h"
 #include "fields.h"
 
 namespace wd {
@@ -39,10 +40,10 @@ size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
 // Plain FP64 CG keeps r, p, t, Ap in FP64 (the true-residual recompute reuses
 // r and t); mixed CG adds FP64 r and t and the FP32 solution accumulator.
-CgLayout cg_layout(const int32_t dims[4], int slots, int inner) {
+CgLayout cg_layout(const int32_t dims[4], int slots, int inner, bool eo) {
   CgLayout w;
-  const long V = static_cast<long>(dims[0]) * dims[1] * dims[2] * dims[3];
-  w.nslices = cg_fuse_slices(dims, inner);
+  const long V = static_cast<long>(dims[0]) * dims[1] * dims[2] * dims[3] / (eo ? 2 : 1);
+  w.nslices = eo ? 0 : cg_fuse_slices(dims, inner);
   const size_t hi = align256(static_cast<size_t>(packed_sites(V)) * slots * spinor_site_bytes(WD_FP64));
   const size_t lo = align256(static_cast<size_t>(packed_sites(V)) * slots * spinor_site_bytes(inner));
   const size_t acc = align256(static_cast<size_t>(packed_sites(V)) * slots * spinor_site_bytes(WD_FP32));
@@ -62,6 +63,15 @@ CgLayout cg_layout(const int32_t dims[4], int slots, int inner) {
   if (inner == WD_FP64) {
     w.r_hi = w.r;
     w.t_hi = w.t;
+  }
+  if (eo) {
+    w.e_lo = o; o += lo;
+    if (inner != WD_FP64) {
+      w.e_hi = o;
+      o += hi;
+    } else {
+      w.e_hi = w.e_lo;
+    }
   }
   w.partials = o; o += align256(static_cast<size_t>(slots) * kMaxPartials * sizeof(double));
   w.pap = o; o += align256(static_cast<size_t>(slots) * kMaxPartials * sizeof(double));
@@ -93,17 +103,25 @@ char* at(void* base, size_t off) { return static_cast<char*>(base) + off; }
 CgEngine::CgEngine(const wd_gauge* ghi, const wd_gauge* glo, int inner, int slots, const void* b,
                    void* x, void* ws, hipStream_t st)
     : ghi_(ghi), glo_(glo ? glo : ghi), inner_(inner), slots_(slots), b_(b), x_(x), ws_(ws), st_(st) {
-  V_ = ghi->V;
+  eo_ = ghi->eo != 0;
+  V_ = eo_ ? ghi->V / 2 : ghi->V;
   nhi_ = packed_sites(V_) * 12;
   nlo_ = inner_ == WD_FP64 ? spinor_units<double>(V_)
                            : inner_ == WD_FP32 ? spinor_units<float>(V_) : spinor_units<_Float16>(V_);
   n32_ = spinor_units<float>(V_);
-  lay_ = cg_layout(ghi->dims, slots, inner_);
+  lay_ = cg_layout(ghi->dims, slots, inner_, eo_);
   partials_ = reinterpret_cast<double*>(at(ws_, lay_.partials));
   rr_ = reinterpret_cast<double*>(at(ws_, lay_.rr));
   paps_ = reinterpret_cast<double*>(at(ws_, lay_.paps));
   pap_ = reinterpret_cast<double*>(at(ws_, lay_.pap));
   scal_ = reinterpret_cast<double*>(at(ws_, lay_.scal));
+}
+
+int CgEngine::apply_q(const wd_gauge* g, const double* m, const RhsSet& set, const void* in, void* tmp,
+                      void* out, const char* what) const {
+  return launch_status(eo_ ? launch_schur_q(g, m, set, in, tmp, out, st_)
+                           : launch_dslash_multi(g, m, set.n, set.idx, in, out, WD_FLAG_GAMMA5, st_),
+                       what);
 }
 
 int CgEngine::start(const RhsSet& set, bool x0_given) {
@@ -181,11 +199,8 @@ int CgEngine::iterate(const RhsSet& set) {
                          "cg: x, p");
     return rc;
   }
-  int rc = launch_status(launch_dslash_multi(glo_, m, set.n, set.idx, at(ws_, lay_.p),
-                                             at(ws_, lay_.t), WD_FLAG_GAMMA5, st_), "cg: Q p");
-  if (rc == WD_OK)
-    rc = launch_status(launch_dslash_multi(glo_, m, set.n, set.idx, at(ws_, lay_.t),
-                                           at(ws_, lay_.ap), WD_FLAG_GAMMA5, st_), "cg: Q Q p");
+  int rc = apply_q(glo_, m, set, at(ws_, lay_.p), at(ws_, lay_.e_lo), at(ws_, lay_.t), "cg: Q p");
+  if (rc == WD_OK) rc = apply_q(glo_, m, set, at(ws_, lay_.t), at(ws_, lay_.e_lo), at(ws_, lay_.ap), "cg: Q Q p");
   // <p, A p> = |Q p|^2: partial sums here, reduced (with alpha) inside the r update
   int npap = 0;
   if (rc == WD_OK)
@@ -218,12 +233,9 @@ int CgEngine::refresh(const RhsSet& set) {
   int rc = WD_OK;
   if (inner_ != WD_FP64)  // the FP32 accumulator joins the FP64 solution
     rc = launch_status(blas_flush_x(x_, at(ws_, lay_.x_lo), n32_, nhi_, set, st_), "cg: flush x");
+  if (rc == WD_OK) rc = apply_q(ghi_, m, set, x_, at(ws_, lay_.e_hi), at(ws_, lay_.t_hi), "cg: Q x");
   if (rc == WD_OK)
-    rc = launch_status(launch_dslash_multi(ghi_, m, set.n, set.idx, x_, at(ws_, lay_.t_hi),
-                                           WD_FLAG_GAMMA5, st_), "cg: Q x");
-  if (rc == WD_OK)
-    rc = launch_status(launch_dslash_multi(ghi_, m, set.n, set.idx, at(ws_, lay_.t_hi),
-                                           at(ws_, lay_.r_hi), WD_FLAG_GAMMA5, st_), "cg: Q Q x");
+    rc = apply_q(ghi_, m, set, at(ws_, lay_.t_hi), at(ws_, lay_.e_hi), at(ws_, lay_.r_hi), "cg: Q Q x");
   if (rc == WD_OK)
     rc = launch_status(blas_residual(at(ws_, lay_.r_hi), b_, nhi_, V_, set, partials_, scal_, st_),
                        "cg: b - A x");
@@ -241,13 +253,6 @@ int CgEngine::fetch_scalars(double* host) const {
 }
 
 namespace {
-
-RhsSet set_of(const std::vector<int>& ks) {
-  RhsSet s{};
-  s.n = static_cast<int>(ks.size());
-  for (size_t i = 0; i < ks.size(); ++i) s.idx[i] = ks[i];
-  return s;
-}
 
 // Chunks of CG iterations captured as HIP graphs and replayed: one graph per
 // (set of active right-hand sides, chunk length). The scalars never leave the
@@ -327,7 +332,8 @@ class OwnStream {
 // completed (a device error), which is dropped.
 class HostScalars {
  public:
-  HostScalars() {
+  explicit HostScalars(bool take) {
+    if (!take) return;
     {
       std::lock_guard<std::mutex> lk(mu());
       if (!pool().empty()) {
@@ -378,13 +384,35 @@ hipError_t poll_stream(hipStream_t st) {
   }
 }
 
+}  // namespace
+
+// Right-hand-side indices of a solve, in a fixed-capacity list (no heap use).
+struct IdxList {
+  int n = 0;
+  int k[kMaxRhs] = {};
+  void push(int v) { k[n++] = v; }
+  bool has(int v) const {
+    for (int i = 0; i < n; ++i)
+      if (k[i] == v) return true;
+    return false;
+  }
+  RhsSet set() const {
+    RhsSet s{};
+    s.n = n;
+    for (int i = 0; i < n; ++i) s.idx[i] = k[i];
+    return s;
+  }
+};
+
 // The synchronous solver: all right-hand sides start together; every
 // check_every iterations the host reads the scalars, recomputes the true
 // residual of those that need it, and drops the finished ones. With
 // use_graph, each chunk of iterations between two reads is a graph replay.
+// host: where the scalars are read to (kMaxRhs * kScalars doubles), or null
+// for a page-locked buffer from the pool.
 int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, int nrhs,
                const void* b, void* x, const wd_cg_params& prm, wd_cg_stats* stats, void* ws,
-               hipStream_t caller) {
+               hipStream_t caller, double* host) {
   const auto t_start = std::chrono::steady_clock::now();
   std::unique_ptr<OwnStream> own;
   if (prm.use_graph) {
@@ -396,11 +424,12 @@ int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, i
   if (own) graphs = std::make_unique<ChunkGraphs>(st);
   CgEngine eng(ghi, glo, prm.inner, nrhs, b, x, ws, st);
   for (int k = 0; k < nrhs; ++k) eng.set_mass(k, masses[k]);
-  HostScalars hs;
-  if (hs.get() == nullptr) return set_error(WD_ERR_NOMEM, "cg: cannot allocate page-locked host memory");
-  auto sc = [&](int k) { return hs.get() + static_cast<size_t>(k) * kScalars; };
+  HostScalars hs(host == nullptr);
+  double* const scal = host != nullptr ? host : hs.get();
+  if (scal == nullptr) return set_error(WD_ERR_NOMEM, "cg: cannot allocate page-locked host memory");
+  auto sc = [&](int k) { return scal + static_cast<size_t>(k) * kScalars; };
   auto read = [&]() -> int {
-    const int rc = eng.fetch_scalars(hs.get());
+    const int rc = eng.fetch_scalars(scal);
     if (rc != WD_OK) {
       hs.drop();
       return rc;
@@ -410,24 +439,29 @@ int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, i
     hs.drop();
     return set_error(WD_ERR_DEVICE, "cg: device error: %s", hipGetErrorString(e));
   };
-  std::vector<int> status(nrhs, WD_PENDING), iters(nrhs, 0), updates(nrhs, 0), all;
-  for (int k = 0; k < nrhs; ++k) all.push_back(k);
+  int status[kMaxRhs], iters[kMaxRhs], updates[kMaxRhs];
+  IdxList all;
+  for (int k = 0; k < nrhs; ++k) {
+    status[k] = WD_PENDING;
+    iters[k] = updates[k] = 0;
+    all.push(k);
+  }
   const bool mixed = prm.inner != WD_FP64;
 
-  int rc = eng.start(set_of(all), prm.x0_given != 0);
+  int rc = eng.start(all.set(), prm.x0_given != 0);
   if (rc == WD_OK) rc = read();
-  std::vector<int> active;
+  IdxList active;
   for (int k = 0; rc == WD_OK && k < nrhs; ++k) {
     const double b2 = sc(k)[kB2], rr = sc(k)[kRr];
     if (!std::isfinite(b2) || !std::isfinite(rr)) status[k] = WD_ERR_NUMERIC;
     else if (b2 == 0.0 || rr <= prm.tol * prm.tol * b2) status[k] = WD_OK;
-    else active.push_back(k);
+    else active.push(k);
   }
   int it = 0;
-  while (rc == WD_OK && !active.empty() && it < prm.max_iter) {
+  while (rc == WD_OK && active.n > 0 && it < prm.max_iter) {
     // iterations up to the next check (a multiple of check_every, or max_iter)
     const int n = std::min(prm.check_every - it % prm.check_every, prm.max_iter - it);
-    const RhsSet set = set_of(active);
+    const RhsSet set = active.set();
     if (graphs) {
       rc = graphs->run(eng, set, n);
     } else {
@@ -435,23 +469,25 @@ int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, i
     }
     if (rc != WD_OK) break;
     it += n;
-    for (int k : active) iters[k] = it;
+    for (int i = 0; i < active.n; ++i) iters[active.k[i]] = it;
     const bool at_max = it >= prm.max_iter;
     if ((rc = read()) != WD_OK) break;
-    std::vector<int> refresh, keep;
-    for (int k : active) {
+    IdxList refresh, keep;
+    for (int i = 0; i < active.n; ++i) {
+      const int k = active.k[i];
       const CgAction a = cg_check(sc(k), prm.tol, mixed, prm.delta, at_max);
       if (a == kCgNumeric) { status[k] = WD_ERR_NUMERIC; continue; }
-      if (a == kCgRefresh) refresh.push_back(k);
-      keep.push_back(k);
+      if (a == kCgRefresh) refresh.push(k);
+      keep.push(k);
     }
     active = keep;
-    if (refresh.empty()) continue;
-    if ((rc = eng.refresh(set_of(refresh))) != WD_OK || (rc = read()) != WD_OK) break;
-    std::vector<int> still;
-    for (int k : active) {
-      if (std::find(refresh.begin(), refresh.end(), k) == refresh.end()) {
-        still.push_back(k);
+    if (refresh.n == 0) continue;
+    if ((rc = eng.refresh(refresh.set())) != WD_OK || (rc = read()) != WD_OK) break;
+    IdxList still;
+    for (int i = 0; i < active.n; ++i) {
+      const int k = active.k[i];
+      if (!refresh.has(k)) {
+        still.push(k);
         continue;
       }
       ++updates[k];
@@ -459,13 +495,13 @@ int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, i
         case kCgConverged: status[k] = WD_OK; break;
         case kCgFailed: status[k] = WD_ERR_NUMERIC; break;
         case kCgNotConverged: status[k] = WD_ERR_NOT_CONVERGED; break;
-        case kCgKeepGoing: still.push_back(k); break;
+        case kCgKeepGoing: still.push(k); break;
       }
     }
     active = still;
   }
   if (rc == WD_OK) {
-    for (int k : active) status[k] = WD_ERR_NOT_CONVERGED;
+    for (int i = 0; i < active.n; ++i) status[active.k[i]] = WD_ERR_NOT_CONVERGED;
     rc = read();
   }
   if (rc != WD_OK) {
@@ -494,6 +530,44 @@ int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, i
   return worst;
 }
 
+namespace {
+
+// Argument checks of the synchronous solver, shared by its two entry points;
+// on success *vec is the bytes of b_dev and x_dev and *need the workspace's.
+int check_solve_args(const wd_gauge* g_hi, const wd_gauge* g_lo, const double* masses, int32_t nrhs,
+                     const void* b_dev, const void* x_dev, const wd_cg_params* params, size_t* vec,
+                     size_t* need) {
+  int rc = check_gauge(g_hi);
+  if (rc != WD_OK) return rc;
+  if ((rc = check_layout(g_hi, 0, "cg_solve_normal")) != WD_OK) return rc;
+  if (g_hi->prec != WD_FP64) return set_error(WD_ERR_INVALID_ARG, "g_hi must be an FP64 gauge field");
+  if (params == nullptr || masses == nullptr)
+    return set_error(WD_ERR_INVALID_ARG, "params and masses_host must not be NULL");
+  const wd_cg_params& p = *params;
+  if (nrhs < 1 || nrhs > kMaxRhs) return set_error(WD_ERR_UNSUPPORTED, "nrhs %d outside 1..%d", nrhs, kMaxRhs);
+  if (!(p.tol > 0.0) || p.max_iter < 1 || p.check_every < 1)
+    return set_error(WD_ERR_INVALID_ARG, "need tol > 0, max_iter >= 1, check_every >= 1");
+  if (p.inner != WD_FP64 && p.inner != WD_FP32 && p.inner != WD_FP16)
+    return set_error(WD_ERR_INVALID_ARG, "unknown inner precision %d", p.inner);
+  if (p.inner != WD_FP64) {
+    if ((rc = check_gauge(g_lo)) != WD_OK) return rc;
+    if ((rc = check_layout(g_lo, 0, "cg_solve_normal")) != WD_OK) return rc;
+    if (g_lo->prec != p.inner)
+      return set_error(WD_ERR_INVALID_ARG, "g_lo must be a gauge field of the inner precision %d", p.inner);
+    for (int i = 0; i < 4; ++i)
+      if (g_lo->dims[i] != g_hi->dims[i]) return set_error(WD_ERR_SHAPE, "g_lo and g_hi have different lattices");
+    if (!(p.delta > 0.0 && p.delta < 1.0)) return set_error(WD_ERR_INVALID_ARG, "delta must lie in (0, 1)");
+  }
+  for (int k = 0; k < nrhs; ++k)
+    if (!std::isfinite(masses[k])) return set_error(WD_ERR_INVALID_ARG, "mass %d is not finite", k);
+  *vec = static_cast<size_t>(packed_sites(g_hi->V)) * nrhs * spinor_site_bytes(WD_FP64);
+  if ((rc = check_device_range(b_dev, *vec, "b_dev")) != WD_OK) return rc;
+  if ((rc = check_device_range(x_dev, *vec, "x_dev")) != WD_OK) return rc;
+  if (overlaps(b_dev, *vec, x_dev, *vec)) return set_error(WD_ERR_INVALID_ARG, "b_dev and x_dev overlap");
+  *need = cg_layout(g_hi->dims, nrhs, p.inner).bytes;
+  return WD_OK;
+}
+
 }  // namespace
 }  // namespace wd
 
@@ -513,44 +587,16 @@ int cg_solve_normal(const wd_gauge* g_hi, const wd_gauge* g_lo, const double* ma
                     wd_cg_stats* stats_host, void* ws_dev, size_t ws_bytes, hipStream_t stream) {
   try {
     clear_error();
-    int rc = check_gauge(g_hi);
+    size_t vec = 0, need = 0;
+    int rc = check_solve_args(g_hi, g_lo, masses_host, nrhs, b_dev, x_dev, params, &vec, &need);
     if (rc != WD_OK) return rc;
-    if (g_hi->prec != WD_FP64) return set_error(WD_ERR_INVALID_ARG, "g_hi must be an FP64 gauge field");
-    if (params == nullptr || masses_host == nullptr)
-      return set_error(WD_ERR_INVALID_ARG, "params and masses_host must not be NULL");
-    const wd_cg_params& p = *params;
-    if (nrhs < 1 || nrhs > kMaxRhs)
-      return set_error(WD_ERR_UNSUPPORTED, "nrhs %d outside 1..%d", nrhs, kMaxRhs);
-    if (!(p.tol > 0.0) || p.max_iter < 1 || p.check_every < 1)
-      return set_error(WD_ERR_INVALID_ARG, "need tol > 0, max_iter >= 1, check_every >= 1");
-    if (p.inner != WD_FP64 && p.inner != WD_FP32 && p.inner != WD_FP16)
-      return set_error(WD_ERR_INVALID_ARG, "unknown inner precision %d", p.inner);
-    if (p.inner != WD_FP64) {
-      if ((rc = check_gauge(g_lo)) != WD_OK) return rc;
-      if (g_lo->prec != p.inner)
-        return set_error(WD_ERR_INVALID_ARG, "g_lo must be a gauge field of the inner precision %d",
-                         p.inner);
-      for (int i = 0; i < 4; ++i)
-        if (g_lo->dims[i] != g_hi->dims[i])
-          return set_error(WD_ERR_SHAPE, "g_lo and g_hi have different lattices");
-      if (!(p.delta > 0.0 && p.delta < 1.0))
-        return set_error(WD_ERR_INVALID_ARG, "delta must lie in (0, 1)");
-    }
-    for (int k = 0; k < nrhs; ++k)
-      if (!std::isfinite(masses_host[k]))
-        return set_error(WD_ERR_INVALID_ARG, "mass %d is not finite", k);
-    const long V = g_hi->V;
-    const size_t vec = static_cast<size_t>(packed_sites(V)) * nrhs * spinor_site_bytes(WD_FP64);
-    if ((rc = check_device_range(b_dev, vec, "b_dev")) != WD_OK) return rc;
-    if ((rc = check_device_range(x_dev, vec, "x_dev")) != WD_OK) return rc;
-    const size_t need = cg_layout(g_hi->dims, nrhs, p.inner).bytes;
     if (ws_bytes < need) return set_error(WD_ERR_INVALID_ARG, "ws_bytes %zu < %zu needed", ws_bytes, need);
     if ((rc = check_device_range(ws_dev, need, "ws_dev")) != WD_OK) return rc;
-    if (overlaps(b_dev, vec, x_dev, vec) || overlaps(b_dev, vec, ws_dev, need) ||
-        overlaps(x_dev, vec, ws_dev, need))
+    if (overlaps(b_dev, vec, ws_dev, need) || overlaps(x_dev, vec, ws_dev, need))
       return set_error(WD_ERR_INVALID_ARG, "b_dev, x_dev and ws_dev must not overlap");
+    const wd_cg_params& p = *params;
     return solve_sync(g_hi, p.inner != WD_FP64 ? g_lo : g_hi, masses_host, nrhs, b_dev, x_dev, p,
-                      stats_host, ws_dev, stream);
+                      stats_host, ws_dev, stream, nullptr);
   } catch (...) {
     return set_error(WD_ERR_INTERNAL, "unexpected exception in cg_solve_normal");
   }

@@ -13,13 +13,16 @@ namespace wd {
 // iteration's vector work is fused into its applications of Q (nslices > 0),
 // paps and rr hold the |Q p|^2 and <r,r> partial sums of the tile slices, and
 // (FP32 arithmetic, where the update is fused too) A p is never stored.
+// With eo (an even-odd gauge field) the vectors are odd half fields of V/2
+// sites, A = (gamma5 S)^2 with the odd-site Schur complement S, and e_lo /
+// e_hi are the even half fields each application of gamma5 S passes through.
 struct CgLayout {
   size_t bytes = 0;
   size_t r_hi = 0, t_hi = 0, x_lo = 0, r = 0, p = 0, t = 0, ap = 0, partials = 0, pap = 0, scal = 0,
-         rr = 0, paps = 0;
+         rr = 0, paps = 0, e_lo = 0, e_hi = 0;
   int nslices = 0;
 };
-CgLayout cg_layout(const int32_t dims[4], int slots, int inner);
+CgLayout cg_layout(const int32_t dims[4], int slots, int inner, bool eo = false);
 
 size_t align256(size_t b);
 
@@ -32,8 +35,9 @@ enum CgOutcome { kCgKeepGoing, kCgConverged, kCgNotConverged, kCgFailed };
 CgAction cg_check(const double* sc, double tol, bool mixed, double delta, bool at_max);
 CgOutcome cg_after_refresh(const double* sc, double tol, bool at_max);
 
-// CG on D^dag D for up to kMaxRhs slots that share one lattice and gauge
-// field. Slot k's vectors are field k of each buffer: b and x (FP64 packed,
+// CG on D^dag D (or, with an even-odd gauge field, on S^dag S for the
+// odd-site Schur complement S) for up to kMaxRhs slots that share one lattice
+// and gauge field. Slot k's vectors are field k of each buffer: b and x (FP64 packed,
 // caller- or server-owned) and the workspace. Every method only enqueues
 // work on the stream and returns a wd_status.
 class CgEngine {
@@ -57,6 +61,10 @@ class CgEngine {
   int fetch_scalars(double* host) const;
 
  private:
+  // out = Q in (Q = gamma5 D, or gamma5 S through the even fields tmp)
+  int apply_q(const wd_gauge* g, const double* m, const RhsSet& set, const void* in, void* tmp, void* out,
+              const char* what) const;
+  bool eo_ = false;
   const wd_gauge* ghi_;
   const wd_gauge* glo_;
   int inner_;
@@ -74,5 +82,14 @@ class CgEngine {
   double* scal_ = nullptr;
   double masses_[kMaxRhs] = {};
 };
+
+// The synchronous solver behind cg_solve_normal: all right-hand sides start
+// together, the host checks the scalars every check_every iterations (into
+// `host`, kMaxRhs * kScalars doubles, or a page-locked buffer of a pool when
+// null) and recomputes true residuals as the engine asks. Arguments are
+// checked by the caller.
+int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, int nrhs, const void* b,
+               void* x, const wd_cg_params& prm, wd_cg_stats* stats, void* ws, hipStream_t caller,
+               double* host);
 
 }  // namespace wd

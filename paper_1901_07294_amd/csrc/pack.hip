@@ -1,25 +1,22 @@
 // Conversion between the canonical complex128 layouts of the C ABI and the
 // packed structure-of-arrays layouts of fields.h (once per field, outside the
 // operator application).
+#include "blas.h"
 #include "fields.h"
 #include "wd_internal.h"
 
 namespace wd {
 namespace {
 
-// One thread per (right-hand side, site). The canonical spinor of a site is 12
-// consecutive complex128 values (192 B); the packed planes are written
-// coalesced. T is the storage type.
+// FP64 link entry -> binary16, rounded once to nearest even.
+__device__ __forceinline__ _Float16 to_half(double v) { return static_cast<_Float16>(v); }
+
+
+// Site s of a packed spinor field d (storage T) from its 12 canonical
+// complex128 values.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void pack_spinor_kernel(const double2* __restrict__ canon,
-                                                             typename Packed<T>::S* __restrict__ dst,
-                                                             long V, long total) {
-  const long i = static_cast<long>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= total) return;
-  const long k = i / V;
-  const long s = i - k * V;
-  const double2* src = canon + i * 12;
-  typename Packed<T>::S* d = dst + k * spinor_units<T>(V);
+__device__ __forceinline__ void pack_site(const double2* __restrict__ src, typename Packed<T>::S* __restrict__ d,
+                                          long s, long V) {
   if constexpr (sizeof(T) == 8) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) d[pidx(s, c, 12, V)] = src[c];
@@ -39,15 +36,10 @@ __global__ __launch_bounds__(kBlock) void pack_spinor_kernel(const double2* __re
   }
 }
 
+// The 12 canonical complex128 values of site s of a packed spinor field p.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void unpack_spinor_kernel(
-    const typename Packed<T>::S* __restrict__ src, double2* __restrict__ canon, long V, long total) {
-  const long i = static_cast<long>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= total) return;
-  const long k = i / V;
-  const long s = i - k * V;
-  double2* d = canon + i * 12;
-  const typename Packed<T>::S* p = src + k * spinor_units<T>(V);
+__device__ __forceinline__ void unpack_site(const typename Packed<T>::S* __restrict__ p,
+                                            double2* __restrict__ d, long s, long V) {
   if constexpr (sizeof(T) == 8) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) d[c] = p[pidx(s, c, 12, V)];
@@ -66,19 +58,35 @@ __global__ __launch_bounds__(kBlock) void unpack_spinor_kernel(
   }
 }
 
-// FP64 link entry -> binary16, rounded once to nearest even.
-__device__ __forceinline__ _Float16 to_half(double v) { return static_cast<_Float16>(v); }
-
-// One thread per (site, direction). Canonical links of a site are 4 x 9
-// consecutive complex128 values.
-template <typename T, bool C12>
-__global__ __launch_bounds__(kBlock) void pack_gauge_kernel(const double2* __restrict__ canon,
-                                                            void* __restrict__ dst, long V) {
+// One thread per (right-hand side, site). The canonical spinor of a site is 12
+// consecutive complex128 values (192 B); the packed planes are written
+// coalesced. T is the storage type.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pack_spinor_kernel(const double2* __restrict__ canon,
+                                                             typename Packed<T>::S* __restrict__ dst,
+                                                             long V, long total) {
   const long i = static_cast<long>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= 4 * V) return;
-  const long s = i >> 2;
-  const int mu = static_cast<int>(i & 3);
-  const double2* src = canon + i * 9;
+  if (i >= total) return;
+  const long k = i / V;
+  const long s = i - k * V;
+  pack_site<T>(canon + i * 12, dst + k * spinor_units<T>(V), s, V);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void unpack_spinor_kernel(
+    const typename Packed<T>::S* __restrict__ src, double2* __restrict__ canon, long V, long total) {
+  const long i = static_cast<long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= total) return;
+  const long k = i / V;
+  const long s = i - k * V;
+  unpack_site<T>(src + k * spinor_units<T>(V), canon + i * 12, s, V);
+}
+
+// Link mu of site s of a packed gauge field dst (storage T) from its 9
+// canonical complex128 entries.
+template <typename T, bool C12>
+__device__ __forceinline__ void pack_link(const double2* __restrict__ src, void* __restrict__ dst, long s,
+                                          int mu, long V) {
   if constexpr (sizeof(T) == 8) {
     constexpr int n = C12 ? 6 : 9;
     double2* d = static_cast<double2*>(dst);
@@ -111,6 +119,102 @@ __global__ __launch_bounds__(kBlock) void pack_gauge_kernel(const double2* __res
 #pragma unroll
     for (int k = 0; k < 9; ++k)
       d[pidx<kHalfBlock>(s, mu * 9 + k, 36, V)] = h2{to_half(src[k].x), to_half(src[k].y)};
+  }
+}
+
+// One thread per (site, direction). Canonical links of a site are 4 x 9
+// consecutive complex128 values.
+template <typename T, bool C12>
+__global__ __launch_bounds__(kBlock) void pack_gauge_kernel(const double2* __restrict__ canon,
+                                                            void* __restrict__ dst, long V) {
+  const long i = static_cast<long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= 4 * V) return;
+  pack_link<T, C12>(canon + i * 9, dst, i >> 2, static_cast<int>(i & 3), V);
+}
+
+// ----------------------------------------------------------- even-odd layout
+//
+// A field split by site parity (x+y+z+t) mod 2 keeps the sites of each parity
+// as a packed field of Vh = V/2 sites (the layouts above), in half-site order
+// h = xh + (X/2) * (y + Y * (z + Z * t)) with x = 2 xh + ((y + z + t + parity) & 1).
+
+// Canonical site index of half site h of parity q.
+__device__ __forceinline__ long eo_site(const EoGeo& g, long h, int q) {
+  const long xh = h % g.Xh;
+  const long r = h / g.Xh;  // y + Y (z + Z t)
+  const int y = static_cast<int>(r % g.Y);
+  const int z = static_cast<int>((r / g.Y) % g.Z);
+  const int t = static_cast<int>(r / (static_cast<long>(g.Y) * g.Z));
+  return 2 * xh + ((y + z + t + q) & 1) + static_cast<long>(g.X) * r;
+}
+
+// One thread per (parity, half site, direction): both parities' links, each
+// a packed gauge field of Vh sites, even first, `half` bytes apart.
+template <typename T, bool C12>
+__global__ __launch_bounds__(kBlock) void pack_gauge_eo_kernel(const double2* __restrict__ canon,
+                                                               char* __restrict__ dst, EoGeo g,
+                                                               size_t half) {
+  const long i = static_cast<long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= 8L * g.Vh) return;
+  const int q = static_cast<int>(i / (4L * g.Vh));
+  const long j = i - q * 4L * g.Vh;
+  const long h = j >> 2;
+  const int mu = static_cast<int>(j & 3);
+  pack_link<T, C12>(canon + (eo_site(g, h, q) * 4 + mu) * 9, dst + q * half, h, mu, g.Vh);
+}
+
+// Sites of parity q of canonical spinors -> packed half fields, and back (the
+// sites of the other parity of the canonical array are set to zero).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pack_spinor_eo_kernel(const double2* __restrict__ canon,
+                                                                typename Packed<T>::S* __restrict__ dst,
+                                                                EoGeo g, int q, long total) {
+  const long i = static_cast<long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= total) return;
+  const long k = i / g.Vh;
+  const long h = i - k * g.Vh;
+  const long V = 2L * g.Vh;
+  pack_site<T>(canon + (k * V + eo_site(g, h, q)) * 12, dst + k * spinor_units<T>(g.Vh), h, g.Vh);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void unpack_spinor_eo_kernel(
+    const typename Packed<T>::S* __restrict__ src, double2* __restrict__ canon, EoGeo g, int q, long total) {
+  const long i = static_cast<long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= total) return;
+  const long k = i / g.Vh;
+  const long h = i - k * g.Vh;
+  const long V = 2L * g.Vh;
+  double2* site = canon + (k * V + eo_site(g, h, q)) * 12;
+  unpack_site<T>(src + k * spinor_units<T>(g.Vh), site, h, g.Vh);
+  double2* other = canon + (k * V + eo_site(g, h, q ^ 1)) * 12;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) other[c] = make_double2(0.0, 0.0);
+}
+
+// Packed FP64 full-lattice fields <-> their two packed FP64 half fields (even,
+// odd), one thread per (right-hand side, parity, half site). Field k of each
+// is at k * (its 16-byte elements per field).
+__global__ __launch_bounds__(kBlock) void split_eo_kernel(const double2* __restrict__ full,
+                                                          double2* __restrict__ even,
+                                                          double2* __restrict__ odd, EoGeo g,
+                                                          RhsSet set, bool merge) {
+  const long i = static_cast<long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= 2L * g.Vh) return;
+  const int q = static_cast<int>(i / g.Vh);
+  const long h = i - q * g.Vh;
+  const long V = 2L * g.Vh;
+  const long k = set.idx[blockIdx.y];
+  const long s = eo_site(g, h, q);
+  const double2* f = full + k * spinor_units<double>(V);
+  double2* p = (q == 0 ? even : odd) + k * spinor_units<double>(g.Vh);
+  if (merge) {
+    double2* fo = const_cast<double2*>(f);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) fo[pidx(s, c, 12, V)] = p[pidx(h, c, 12, g.Vh)];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[pidx(h, c, 12, g.Vh)] = f[pidx(s, c, 12, V)];
   }
 }
 
@@ -161,6 +265,60 @@ hipError_t launch_pack_spinor(const void* canon, void* dst, const Geo& geo, int 
     case WD_FP16: pack_spinor_t<_Float16>(src, dst, V, total, s); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+size_t eo_gauge_half_bytes(long Vh, int prec, int c12) {
+  return static_cast<size_t>(packed_sites(Vh)) * gauge_site_bytes(prec, c12);
+}
+
+hipError_t launch_pack_gauge_eo(const void* canon, void* dst, const EoGeo& g, int prec, int c12,
+                                hipStream_t s) {
+  const auto* src = static_cast<const double2*>(canon);
+  char* d = static_cast<char*>(dst);
+  const size_t half = eo_gauge_half_bytes(g.Vh, prec, c12);
+  const unsigned nb = blocks_for(8L * g.Vh);
+#define WD_EO_PACK(T)                                                                     \
+  if (c12) pack_gauge_eo_kernel<T, true><<<nb, kBlock, 0, s>>>(src, d, g, half);          \
+  else pack_gauge_eo_kernel<T, false><<<nb, kBlock, 0, s>>>(src, d, g, half);
+  switch (prec) {
+    case WD_FP64: WD_EO_PACK(double) break;
+    case WD_FP32: WD_EO_PACK(float) break;
+    case WD_FP16: WD_EO_PACK(_Float16) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef WD_EO_PACK
+  return hipGetLastError();
+}
+
+hipError_t launch_spinor_eo(const void* src, void* dst, const EoGeo& g, int prec, int parity, int nrhs,
+                            bool import, hipStream_t s) {
+  const long total = g.Vh * nrhs;
+  if (total == 0) return hipSuccess;
+  const unsigned nb = blocks_for(total);
+#define WD_EO_SPINOR(T)                                                                              \
+  if (import)                                                                                        \
+    pack_spinor_eo_kernel<T><<<nb, kBlock, 0, s>>>(static_cast<const double2*>(src),                 \
+                                                   static_cast<Packed<T>::S*>(dst), g, parity, total); \
+  else                                                                                               \
+    unpack_spinor_eo_kernel<T><<<nb, kBlock, 0, s>>>(static_cast<const Packed<T>::S*>(src),          \
+                                                     static_cast<double2*>(dst), g, parity, total);
+  switch (prec) {
+    case WD_FP64: WD_EO_SPINOR(double) break;
+    case WD_FP32: WD_EO_SPINOR(float) break;
+    case WD_FP16: WD_EO_SPINOR(_Float16) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef WD_EO_SPINOR
+  return hipGetLastError();
+}
+
+hipError_t launch_split_eo(const void* full, void* even, void* odd, const EoGeo& g, const RhsSet& set,
+                           bool merge, hipStream_t s) {
+  if (set.n == 0) return hipSuccess;
+  split_eo_kernel<<<dim3(blocks_for(2L * g.Vh), set.n), kBlock, 0, s>>>(
+      static_cast<const double2*>(full), static_cast<double2*>(even), static_cast<double2*>(odd), g, set,
+      merge);
   return hipGetLastError();
 }
 

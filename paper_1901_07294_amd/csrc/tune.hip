@@ -87,6 +87,7 @@ int wd_tune_dslash(const wd_gauge* g, int32_t nrhs, const void* in_dev, void* ou
   try {
     clear_error();
     int rc = check_gauge(g);
+    if (rc == WD_OK) rc = check_layout(g, 0, "wd_tune_dslash");
     if (rc != WD_OK) return rc;
     if (nrhs < 1 || nrhs > kMaxMultiRhs)
       return set_error(WD_ERR_UNSUPPORTED, "nrhs %d outside 1..%d", nrhs, kMaxMultiRhs);

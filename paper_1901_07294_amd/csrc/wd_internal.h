@@ -15,6 +15,7 @@ struct wd_gauge {
   int64_t V;         // number of sites
   int32_t prec;      // wd_prec of the packed links and of the spinors used with them
   int32_t c12;       // links stored as two rows (12 reals)
+  int32_t eo;        // links split by site parity (wd_gauge_import_eo): even sites' links, then odd
   int device;        // HIP device the packed links live on
   void* links;       // packed links (caller-owned)
   size_t link_bytes;
@@ -55,12 +56,30 @@ inline Geo make_geo(const int32_t d[4]) {
   return g;
 }
 
+// Geometry of a lattice split by site parity (even extents): each parity is a
+// field of Vh = V/2 half sites h = xh + Xh (y + Y (z + Z t)), x = 2 xh +
+// ((y + z + t + parity) & 1).
+struct EoGeo {
+  int X, Y, Z, T, Xh;
+  long Vh;
+};
+
+inline EoGeo make_eo_geo(const int32_t d[4]) {
+  EoGeo g;
+  g.X = d[0]; g.Y = d[1]; g.Z = d[2]; g.T = d[3];
+  g.Xh = g.X / 2;
+  g.Vh = static_cast<long>(g.X) * g.Y * g.Z * g.T / 2;
+  return g;
+}
+
 // Argument checks shared by the entry points (they set the last error).
 int check_dims(const int32_t dims[4], long* V);
 int check_prec(int prec);
 int check_device_range(const void* p, size_t bytes, const char* what);
 bool overlaps(const void* a, size_t na, const void* b, size_t nb);
 int check_gauge(const wd_gauge* g);
+int check_layout(const wd_gauge* g, int eo, const char* what);
+int check_even_dims(const int32_t dims[4]);
 int launch_status(hipError_t e, const char* what);
 
 // Bytes per site of packed fields.
@@ -76,6 +95,15 @@ hipError_t launch_unpack_spinor(const void* src, void* canon, const Geo& geo, in
                                 hipStream_t s);
 hipError_t launch_dslash(const wd_gauge* g, double mass, const void* in, void* out, int flags,
                          hipStream_t s);
+
+// Even-odd layout (pack.hip): bytes of one parity's packed links; packing
+// canonical links into both; spinors of one parity between canonical (the
+// other parity's sites zeroed on export) and packed half fields.
+size_t eo_gauge_half_bytes(long Vh, int prec, int c12);
+hipError_t launch_pack_gauge_eo(const void* canon, void* dst, const EoGeo& g, int prec, int c12,
+                                hipStream_t s);
+hipError_t launch_spinor_eo(const void* src, void* dst, const EoGeo& g, int prec, int parity, int nrhs,
+                            bool import, hipStream_t s);
 // nrhs (1..kMaxMultiRhs) packed fields of `in` / `out`: field fields[i] (or i
 // if fields is null) with mass masses[i].
 hipError_t launch_dslash_multi(const wd_gauge* g, const double* masses, int nrhs, const int* fields,

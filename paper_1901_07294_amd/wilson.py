@@ -36,7 +36,7 @@ WD_FP16 = 2
 
 WD_FLAG_GAMMA5 = 1
 
-ABI_VERSION = 3  # the structures below match this version of include/wilson.h
+ABI_VERSION = 4  # the structures below match this version of include/wilson.h
 
 STATUS_NAMES = {v: k for k, v in dict(globals()).items()
                 if k.startswith("WD_ERR_") or k in ("WD_OK", "WD_PENDING")}
@@ -123,6 +123,18 @@ SIGNATURES = {
     "wd_server_info": (ctypes.c_int, [_vp, ctypes.POINTER(wd_server_state)]),
     "wd_server_destroy": (ctypes.c_int, [_vp]),
     "cg_solve_normal": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp,
+                                       ctypes.POINTER(wd_cg_params), ctypes.POINTER(wd_cg_stats),
+                                       _vp, ctypes.c_size_t, _vp]),
+    "wd_gauge_eo_bytes": (ctypes.c_size_t, [_dims_t, _i32, _i32]),
+    "wd_spinor_eo_bytes": (ctypes.c_size_t, [_dims_t, _i32, _i32]),
+    "wd_gauge_import_eo": (ctypes.c_int, [_dims_t, _vp, _i32, _i32, _vp, ctypes.c_size_t, _vp,
+                                          ctypes.POINTER(_vp)]),
+    "wd_spinor_import_eo": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _vp, _vp]),
+    "wd_spinor_export_eo": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _vp, _vp]),
+    "dslash_apply_eo": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp, _vp,
+                                       _i32, _i32, _vp]),
+    "wilson_workspace_bytes": (ctypes.c_size_t, [_dims_t, _i32, _i32, _i32]),
+    "cg_solve_wilson": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp,
                                        ctypes.POINTER(wd_cg_params), ctypes.POINTER(wd_cg_stats),
                                        _vp, ctypes.c_size_t, _vp]),
     "wd_tune_dslash": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp,
@@ -308,6 +320,58 @@ def cg_solve_normal(g_hi, g_lo, masses, nrhs, b, x, params, ws, ws_bytes=None, s
                               _ptr(x), ctypes.byref(params), stats, _ptr(ws), nb, _stream(stream))
     if check and rc < 0 and rc not in (WD_ERR_NOT_CONVERGED, WD_ERR_NUMERIC):
         raise WilsonError("cg_solve_normal", rc, _L().wd_last_error().decode())
+    return rc, [stats[k].as_dict() for k in range(nrhs)]
+
+
+def wd_gauge_eo_bytes(dims, prec, compress12=0) -> int:
+    return _L().wd_gauge_eo_bytes(_dims(dims), prec, int(bool(compress12)))
+
+
+def wd_spinor_eo_bytes(dims, prec, nrhs=1) -> int:
+    return _L().wd_spinor_eo_bytes(_dims(dims), prec, nrhs)
+
+
+def wd_gauge_import_eo(dims, U_canon, prec, compress12, dst, dst_bytes=None, stream=None) -> Gauge:
+    out = ctypes.c_void_p()
+    nb = _nbytes(dst) if dst_bytes is None else int(dst_bytes)
+    _check("wd_gauge_import_eo", _L().wd_gauge_import_eo(
+        _dims(dims), _ptr(U_canon), prec, int(bool(compress12)), _ptr(dst), nb,
+        _stream(stream), ctypes.byref(out)))
+    return Gauge(out.value, dims, prec, compress12, dst)
+
+
+def wd_spinor_import_eo(g, canon, prec, nrhs, parity, dst, stream=None) -> int:
+    return _check("wd_spinor_import_eo", _L().wd_spinor_import_eo(
+        _h(g), _ptr(canon), prec, nrhs, parity, _ptr(dst), _stream(stream)))
+
+
+def wd_spinor_export_eo(g, src, prec, nrhs, parity, canon, stream=None) -> int:
+    return _check("wd_spinor_export_eo", _L().wd_spinor_export_eo(
+        _h(g), _ptr(src), prec, nrhs, parity, _ptr(canon), _stream(stream)))
+
+
+def dslash_apply_eo(g, masses, nrhs, inp, out, tmp, prec, flags=0, stream=None) -> int:
+    m = (ctypes.c_double * max(1, nrhs))(*[float(v) for v in masses])
+    return _check("dslash_apply_eo", _L().dslash_apply_eo(
+        _h(g), m, nrhs, _ptr(inp), _ptr(out), _ptr(tmp), prec, flags, _stream(stream)))
+
+
+def wilson_workspace_bytes(dims, nrhs, inner, eo) -> int:
+    return _L().wilson_workspace_bytes(_dims(dims), nrhs, inner, int(bool(eo)))
+
+
+def cg_solve_wilson(g_hi, g_lo, masses, nrhs, b, x, params, ws, ws_bytes=None, stream=None,
+                    check=True):
+    """Calls cg_solve_wilson; returns (status, [per right-hand side stats dicts])."""
+    if isinstance(params, dict):
+        params = wd_cg_params(**params)
+    m = (ctypes.c_double * nrhs)(*[float(v) for v in masses])
+    stats = (wd_cg_stats * max(1, nrhs))()
+    nb = _nbytes(ws) if ws_bytes is None else int(ws_bytes)
+    rc = _L().cg_solve_wilson(_h(g_hi), _h(g_lo) if g_lo is not None else None, m, nrhs, _ptr(b),
+                              _ptr(x), ctypes.byref(params), stats, _ptr(ws), nb, _stream(stream))
+    if check and rc < 0 and rc not in (WD_ERR_NOT_CONVERGED, WD_ERR_NUMERIC):
+        raise WilsonError("cg_solve_wilson", rc, _L().wd_last_error().decode())
     return rc, [stats[k].as_dict() for k in range(nrhs)]
 
 

@@ -47,7 +47,7 @@ def test_exports_only_the_abi():
 
 
 def test_version_and_sizes(lib):
-    assert w.wd_abi_version() == 3
+    assert w.wd_abi_version() == 4
     d = (32, 32, 32, 64)
     V = 32 ** 3 * 64
     assert w.wd_spinor_bytes(d, w.WD_FP64, 1) == 192 * V
