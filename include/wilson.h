@@ -362,6 +362,35 @@ WD_API int cg_solve_wilson(const wd_gauge* g_hi, const wd_gauge* g_lo, const dou
                            size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * For callers that cannot allocate memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.
+ * ------------------------------------------------------------------------ */
+
+/* Size of the static device workspace of cg_solve_normal_noalloc (per GPU). */
+#define WD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* cg_solve_normal without a workspace argument. The workspace
+ * (cg_workspace_bytes(dims, nrhs, params->inner) bytes, at most
+ * WD_NOALLOC_SCRATCH_BYTES: e.g. 16^4 with one right-hand side, 8^4 with up to
+ * 16) is a static device array of the library, one per GPU, held from the
+ * first call on that GPU until the process ends. The call allocates nothing:
+ * no hipMalloc, hipFree, hipHostMalloc or allocating library routine (its
+ * first call on a device only looks up that array's address), and the
+ * scalars it reads back land in a static pageable host buffer (one per GPU;
+ * the copy into it waits for the stream). Every call on one GPU shares that
+ * GPU's array and buffer, which keep the last call's contents (a call
+ * initialises what it reads): calls that overlap in time on the same GPU, from
+ * several threads, race and must be serialised by the caller.
+ * params->use_graph is not supported (graph instantiation allocates):
+ * WD_ERR_UNSUPPORTED. A solve needing more workspace than the limit:
+ * WD_ERR_NOMEM (wd_last_error() gives the bytes needed). Arguments, results
+ * and other errors as cg_solve_normal; results are bit-identical to it. */
+WD_API int cg_solve_normal_noalloc(const wd_gauge* g_hi, const wd_gauge* g_lo,
+                                   const double* masses_host, int32_t nrhs, const void* b_dev,
+                                   void* x_dev, const wd_cg_params* params,
+                                   wd_cg_stats* stats_host, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Request server: continuous batching of CG solves (cg_solve_normal's
  * algorithm) on gauge fields kept resident in a caller-given arena.
  *

@@ -34,6 +34,9 @@
 #include "eo.h"
 #include "fields.h"
 
+// Workspace of cg_solve_normal_noalloc (see the note above scratch_address).
+static __device__ __align__(256) unsigned char scratch[WD_NOALLOC_SCRATCH_BYTES];
+
 namespace wd {
 
 size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
@@ -568,6 +571,42 @@ int check_solve_args(const wd_gauge* g_hi, const wd_gauge* g_lo, const double* m
   return WD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Workspace of the entry point that allocates nothing: a static device array,
+// one copy per GPU (the loader places it with the code object on each device;
+// it is held until the process ends). Host code never passes the array's name
+// to a kernel or a copy: it is only a host-side stand-in for the symbol. The
+// device address comes from hipGetSymbolAddress, looked up once per device
+// with that device current, and only that address is used.
+constexpr size_t kScratchBytes = WD_NOALLOC_SCRATCH_BYTES;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+// Scalars of a solve are copied to this pageable host buffer (one per device).
+double g_noalloc_host[kMaxDevices][kMaxRhs * kScalars];
+
+// The scratch array's device address on the current device (looked up on the
+// first call there) and the device index.
+int scratch_address(void** out, int* device) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return set_error(WD_ERR_DEVICE, "no current HIP device");
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(WD_ERR_UNSUPPORTED, "device %d beyond the %d the static workspace serves", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return set_error(WD_ERR_DEVICE, "looking up the static workspace on device %d: %s", dev,
+                       hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  *device = dev;
+  return WD_OK;
+}
+
 }  // namespace
 }  // namespace wd
 
@@ -599,6 +638,30 @@ int cg_solve_normal(const wd_gauge* g_hi, const wd_gauge* g_lo, const double* ma
                       stats_host, ws_dev, stream, nullptr);
   } catch (...) {
     return set_error(WD_ERR_INTERNAL, "unexpected exception in cg_solve_normal");
+  }
+}
+
+int cg_solve_normal_noalloc(const wd_gauge* g_hi, const wd_gauge* g_lo, const double* masses_host,
+                            int32_t nrhs, const void* b_dev, void* x_dev, const wd_cg_params* params,
+                            wd_cg_stats* stats_host, hipStream_t stream) {
+  try {
+    clear_error();
+    size_t vec = 0, need = 0;
+    int rc = check_solve_args(g_hi, g_lo, masses_host, nrhs, b_dev, x_dev, params, &vec, &need);
+    if (rc != WD_OK) return rc;
+    if (params->use_graph)
+      return set_error(WD_ERR_UNSUPPORTED, "use_graph allocates (graph instantiation); not available here");
+    if (need > kScratchBytes)
+      return set_error(WD_ERR_NOMEM, "the solve needs %zu bytes of workspace; the static workspace holds %zu",
+                       need, kScratchBytes);
+    void* ws = nullptr;
+    int dev = 0;
+    if ((rc = scratch_address(&ws, &dev)) != WD_OK) return rc;
+    const wd_cg_params& p = *params;
+    return solve_sync(g_hi, p.inner != WD_FP64 ? g_lo : g_hi, masses_host, nrhs, b_dev, x_dev, p,
+                      stats_host, ws, stream, g_noalloc_host[dev]);
+  } catch (...) {
+    return set_error(WD_ERR_INTERNAL, "unexpected exception in cg_solve_normal_noalloc");
   }
 }
 

@@ -137,6 +137,9 @@ SIGNATURES = {
     "cg_solve_wilson": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp,
                                        ctypes.POINTER(wd_cg_params), ctypes.POINTER(wd_cg_stats),
                                        _vp, ctypes.c_size_t, _vp]),
+    "cg_solve_normal_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double), _i32, _vp,
+                                               _vp, ctypes.POINTER(wd_cg_params),
+                                               ctypes.POINTER(wd_cg_stats), _vp]),
     "wd_tune_dslash": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp,
                                       ctypes.POINTER(wd_tune_result)]),
     "wd_tune_lookup": (ctypes.c_int, [_dims_t, _i32, _i32, _i32, ctypes.POINTER(ctypes.c_int32)]),
@@ -372,6 +375,20 @@ def cg_solve_wilson(g_hi, g_lo, masses, nrhs, b, x, params, ws, ws_bytes=None, s
                               _ptr(x), ctypes.byref(params), stats, _ptr(ws), nb, _stream(stream))
     if check and rc < 0 and rc not in (WD_ERR_NOT_CONVERGED, WD_ERR_NUMERIC):
         raise WilsonError("cg_solve_wilson", rc, _L().wd_last_error().decode())
+    return rc, [stats[k].as_dict() for k in range(nrhs)]
+
+
+def cg_solve_normal_noalloc(g_hi, g_lo, masses, nrhs, b, x, params, stream=None, check=True):
+    """Calls cg_solve_normal_noalloc (the library's static workspace); returns
+    (status, [per right-hand side stats dicts]) as cg_solve_normal does."""
+    if isinstance(params, dict):
+        params = wd_cg_params(**params)
+    m = (ctypes.c_double * nrhs)(*[float(v) for v in masses])
+    stats = (wd_cg_stats * max(1, nrhs))()
+    rc = _L().cg_solve_normal_noalloc(_h(g_hi), _h(g_lo) if g_lo is not None else None, m, nrhs,
+                                      _ptr(b), _ptr(x), ctypes.byref(params), stats, _stream(stream))
+    if check and rc < 0 and rc not in (WD_ERR_NOT_CONVERGED, WD_ERR_NUMERIC):
+        raise WilsonError("cg_solve_normal_noalloc", rc, _L().wd_last_error().decode())
     return rc, [stats[k].as_dict() for k in range(nrhs)]
 
 
