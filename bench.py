@@ -106,7 +106,7 @@ def parse(argv=None):
     ap.add_argument("--c12", action="store_true", help="12-real link compression")
     ap.add_argument("--dims", type=str, default=",".join(map(str, DIMS)))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=80,
+    ap.add_argument("--serve-requests", type=int, default=120,
                     help="requests in the serving measurement (capacity and each load level)")
     ap.add_argument("--tuning", type=str, default=None,
                     help="TB,GW,GROUP,RB: time the operator with this launch instead of the "
@@ -633,7 +633,7 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
             lat_s = np.array([res["t_done"] - res["t_submit"] for rc, res, _ in done.values()])
             wait_s = np.array([res["t_start"] - res["t_submit"] for rc, res, _ in done.values()])
             out["levels"].append({
-                "offered_load": load, "requests": n_req,
+                "offered_load": load, "requests": n_req, "latency_samples": int(len(lat_s)),
                 "ok": int(sum(rc == w.WD_OK for rc, _, _ in done.values())),
                 "req_per_s": round(n_req / wall, 3), "rhs_solves_per_s": round(nrhs_total / wall, 2),
                 "p50_ms": pct(lat_s, 50), "p90_ms": pct(lat_s, 90), "p99_ms": pct(lat_s, 99),

@@ -184,8 +184,10 @@ typedef struct wd_tune_result {
   double best_us;      /* ... and of the choice kept */
 } wd_tune_result;
 
-/* Times every candidate for g's lattice with nrhs right-hand sides (masses
- * 0.1) over reps launches each and registers the fastest eligible one. in_dev
+/* Times every eligible candidate for g's lattice with nrhs right-hand sides
+ * (masses 0.1) in three interleaved rounds of reps launches each, and
+ * registers the one with the fastest round (default_us and best_us are
+ * fastest-round averages). in_dev
  * holds nrhs packed spinors of g's precision; out_dev and ref_dev are scratch
  * buffers of the same size, overwritten. Synchronous on stream; allocates a
  * few bytes of device memory for the comparison. Errors: WD_ERR_INVALID_ARG
