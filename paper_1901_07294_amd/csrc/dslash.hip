@@ -35,6 +35,9 @@
 #ifndef WD_MARCH_WG_PER_CU
 #define WD_MARCH_WG_PER_CU 4  // t-marching workgroups per CU aimed for (LDS permitting)
 #endif
+#ifndef WD_UT_NT
+#define WD_UT_NT 1            // non-temporal loads of the t links in the t-marching kernel
+#endif
 
 namespace wd {
 namespace {
@@ -44,6 +47,7 @@ constexpr int kMarchMaxThreads = 256;       // lanes of a one-right-hand-side ti
 constexpr int kMarchMultiThreads = 768;     // lanes of a several-right-hand-side workgroup
 constexpr int kMarchTargetThreads = WD_MARCH_THREADS;
 constexpr int kMarchWgPerCu = WD_MARCH_WG_PER_CU;
+constexpr bool kUtNt = WD_UT_NT != 0;
 constexpr int kNumCu = 256;
 // Waves of the t-marching kernel a CU holds at once, from the compiled
 // kernels' register use: 256 VGPRs in FP64 (one wave per SIMD), 146-168 with
@@ -360,8 +364,10 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
     // Slice t+1: this workgroup's own spinors (forward t hop, next LDS
     // slice) and, in the same window, the z and off-tile y hops of t+1,
     // whose spinors other workgroups are loading as their own slice now.
+    // U_t(t) serves the forward t hop of t and, from registers, the backward
+    // t hop of t+1: no other workgroup reads it
     cx<R> ut[9];
-    load_link<C12>(links, V, 3, st, ut);
+    load_link<C12, kUtNt>(links, V, 3, st, ut);
     cx<R> nacc[RB][12];
 #pragma unroll
     for (int r = 0; r < RB; ++r)

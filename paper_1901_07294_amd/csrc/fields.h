@@ -254,6 +254,16 @@ __device__ __forceinline__ void lds_load_spinor(const float4* p, int n, int i, c
 
 // -------------------------------------------------------------------- links
 
+typedef float nf2 __attribute__((ext_vector_type(2)));
+
+// One 4- to 16-byte element read with a non-temporal load: for data that no
+// other workgroup reads again, so that its lines displace less of the ones
+// that neighbouring workgroups still have to read from L2.
+template <typename N, typename E>
+__device__ __forceinline__ N nt_load(const E* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const N*>(p));
+}
+
 // Third row of an SU(3) matrix from its first two: r2 = conj(r0 x r1).
 template <typename R>
 __device__ __forceinline__ void rebuild_row2(cx<R> (&u)[9]) {
@@ -262,26 +272,34 @@ __device__ __forceinline__ void rebuild_row2(cx<R> (&u)[9]) {
   u[8] = conj(mul(u[0], u[4]) - mul(u[1], u[3]));
 }
 
-template <bool C12>
+// NT: non-temporal loads (links that no other workgroup reads again).
+template <bool C12, bool NT = false>
 __device__ __forceinline__ void load_link(const double2* __restrict__ p, long V, int mu, int s,
                                           cx<double> (&u)[9]) {
   constexpr int n = C12 ? 6 : 9;
 #pragma unroll
   for (int k = 0; k < n; ++k) {
-    const double2 t = p[pidx(s, mu * n + k, 4 * n, V)];
-    u[k] = {t.x, t.y};
+    const long e = pidx(s, mu * n + k, 4 * n, V);
+    if constexpr (NT) {
+      const nd2 t = nt_load<nd2>(p + e);
+      u[k] = {t.x, t.y};
+    } else {
+      const double2 t = p[e];
+      u[k] = {t.x, t.y};
+    }
   }
   if constexpr (C12) rebuild_row2(u);
 }
 
-template <bool C12>
+template <bool C12, bool NT = false>
 __device__ __forceinline__ void load_link(const float2* __restrict__ p, long V, int mu, int s,
                                           cx<float> (&u)[9]) {
   if constexpr (C12) {
     const float4* q = reinterpret_cast<const float4*>(p);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const float4 t = q[pidx(s, mu * 3 + j, 12, V)];
+      const long e = pidx(s, mu * 3 + j, 12, V);
+      const nf4 t = NT ? nt_load<nf4>(q + e) : nf4{q[e].x, q[e].y, q[e].z, q[e].w};
       u[2 * j] = {t.x, t.y};
       u[2 * j + 1] = {t.z, t.w};
     }
@@ -289,20 +307,22 @@ __device__ __forceinline__ void load_link(const float2* __restrict__ p, long V, 
   } else {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const float2 t = p[pidx(s, mu * 9 + k, 36, V)];
+      const long e = pidx(s, mu * 9 + k, 36, V);
+      const nf2 t = NT ? nt_load<nf2>(p + e) : nf2{p[e].x, p[e].y};
       u[k] = {t.x, t.y};
     }
   }
 }
 
-template <bool C12>
+template <bool C12, bool NT = false>
 __device__ __forceinline__ void load_link(const h2* __restrict__ p, long V, int mu, int s,
                                           cx<float> (&u)[9]) {
   if constexpr (C12) {
     const h4* q = reinterpret_cast<const h4*>(p);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const h4 t = q[pidx<kHalfBlock>(s, mu * 3 + j, 12, V)];
+      const long e = pidx<kHalfBlock>(s, mu * 3 + j, 12, V);
+      const h4 t = NT ? nt_load<h4>(q + e) : q[e];
       u[2 * j] = {static_cast<float>(t.x), static_cast<float>(t.y)};
       u[2 * j + 1] = {static_cast<float>(t.z), static_cast<float>(t.w)};
     }
@@ -310,7 +330,8 @@ __device__ __forceinline__ void load_link(const h2* __restrict__ p, long V, int 
   } else {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const h2 t = p[pidx<kHalfBlock>(s, mu * 9 + k, 36, V)];
+      const long e = pidx<kHalfBlock>(s, mu * 9 + k, 36, V);
+      const h2 t = NT ? nt_load<h2>(p + e) : p[e];
       u[k] = {static_cast<float>(t.x), static_cast<float>(t.y)};
     }
   }
