@@ -38,6 +38,12 @@
 #ifndef WD_UT_NT
 #define WD_UT_NT 1            // non-temporal loads of the t links in the t-marching kernel
 #endif
+#ifndef WD_MARCH_BUF
+#define WD_MARCH_BUF 1        // FP64/FP32 fields below 4 GiB through buffer resources
+#endif
+#ifndef WD_X_SHFL
+#define WD_X_SHFL 1           // backward x links from the neighbour lane (x rows within a wave)
+#endif
 
 namespace wd {
 namespace {
@@ -48,6 +54,8 @@ constexpr int kMarchMultiThreads = 768;     // lanes of a several-right-hand-sid
 constexpr int kMarchTargetThreads = WD_MARCH_THREADS;
 constexpr int kMarchWgPerCu = WD_MARCH_WG_PER_CU;
 constexpr bool kUtNt = WD_UT_NT != 0;
+constexpr bool kMarchBuf = WD_MARCH_BUF != 0;
+constexpr bool kXShfl = WD_X_SHFL != 0;
 constexpr int kNumCu = 256;
 // Waves of the t-marching kernel a CU holds at once, from the compiled
 // kernels' register use: 256 VGPRs in FP64 (one wave per SIMD), 146-168 with
@@ -140,14 +148,29 @@ struct MarchParams {
   int nrhs;    // right-hand sides of the launch
   int gw;      // lane groups per workgroup
   int rb;      // right-hand sides per lane (gw * rb divides nrhs)
+  unsigned link_bytes;    // bytes of the packed links and of one packed spinor field (used
+  unsigned spinor_bytes;  // when they are read through buffer resources, below 4 GiB)
 };
+
+// How the march kernel reaches a field: a plain pointer (any size) or, with
+// BUF, a buffer resource (fields below 4 GiB; no address arithmetic per load).
+template <bool BUF, typename E>
+__device__ __forceinline__ auto field_in(const E* p, unsigned bytes) {
+  if constexpr (BUF) return buf_field(p, bytes);
+  else return p;
+}
+template <bool BUF, typename E>
+__device__ __forceinline__ auto field_out(E* p, unsigned bytes) {
+  if constexpr (BUF) return buf_field(p, bytes);
+  else return p;
+}
 
 // One hop for the RB right-hand sides of a lane: the link (direction MU at
 // site ls) is loaded once and applied to each one's neighbour spinor at site
 // nb. Each right-hand side sees exactly the operations of a one-field hop.
-template <int MU, int S, bool C12, int RB, typename SV, typename LV, typename R>
-__device__ __forceinline__ void hop_rb(const SV* const (&in)[RB], const LV* __restrict__ links, long V,
-                                       int nb, int ls, cx<R> (&acc)[RB][12]) {
+template <int MU, int S, bool C12, int RB, typename SA, typename LA, typename R>
+__device__ __forceinline__ void hop_rb(const SA (&in)[RB], const LA& links, long V, int nb, int ls,
+                                       cx<R> (&acc)[RB][12]) {
   cx<R> u[9];
   load_link<C12>(links, V, MU, ls, u);
 #pragma unroll
@@ -162,10 +185,9 @@ __device__ __forceinline__ void hop_rb(const SV* const (&in)[RB], const LV* __re
 }
 
 // The same with the neighbour spinors read from the LDS slices (slot li).
-template <int MU, int S, bool C12, int RB, typename SL, typename LV, typename R>
-__device__ __forceinline__ void lds_hop_rb(SL* const (&slice)[RB], int n, int li,
-                                           const LV* __restrict__ links, long V, int ls,
-                                           cx<R> (&acc)[RB][12]) {
+template <int MU, int S, bool C12, int RB, typename SL, typename LA, typename R>
+__device__ __forceinline__ void lds_hop_rb(SL* const (&slice)[RB], int n, int li, const LA& links, long V,
+                                           int ls, cx<R> (&acc)[RB][12]) {
   cx<R> u[9];
   load_link<C12>(links, V, MU, ls, u);
 #pragma unroll
@@ -179,12 +201,47 @@ __device__ __forceinline__ void lds_hop_rb(SL* const (&slice)[RB], int n, int li
   }
 }
 
+// The same with the link already in registers.
+template <int MU, int S, int RB, typename SL, typename R>
+__device__ __forceinline__ void lds_hop_u(SL* const (&slice)[RB], int n, int li, const cx<R> (&u)[9],
+                                          cx<R> (&acc)[RB][12]) {
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    cx<R> psi[12];
+    lds_load_spinor(slice[r], n, li, psi);
+    cx<R> h[6], g[6];
+    project<MU, S>(psi, h);
+    su3_mul<(S > 0)>(u, h, g);
+    reconstruct_add<MU, S>(g, acc[r]);
+  }
+}
+
+// Both x hops from LDS. The backward hop's link U_x(x - 1) is the forward
+// hop's link of the lane holding x - 1; with xshfl (every x row lies within
+// one wave: X divides 64) it is taken from that lane with a cross-lane
+// shuffle (the same values, no memory access), otherwise loaded.
+template <bool C12, int RB, typename SL, typename LA, typename R>
+__device__ __forceinline__ void lds_x_hops(SL* const (&slice)[RB], int n, int lxp, int lxm, const LA& links,
+                                           long V, int st, int dxm, bool xshfl, int src_lane,
+                                           cx<R> (&acc)[RB][12]) {
+  cx<R> u[9];
+  load_link<C12>(links, V, 0, st, u);
+  lds_hop_u<0, -1>(slice, n, lxp, u, acc);
+  if (xshfl) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = {__shfl(u[k].re, src_lane, 64), __shfl(u[k].im, src_lane, 64)};
+  } else {
+    load_link<C12>(links, V, 0, st + dxm, u);
+  }
+  lds_hop_u<0, +1>(slice, n, lxm, u, acc);
+}
+
 // Hops of time t that involve sites outside the tile: z forward and
 // backward, and the y hops of the tile's edge rows.
-template <bool C12, int RB, typename SV, typename LV, typename R>
-__device__ __forceinline__ void outer_hops(const SV* const (&in)[RB], const LV* __restrict__ links,
-                                           long V, int st, int dzp, int dzm, bool y_fwd_out, int dyp,
-                                           bool y_bwd_out, int dym, cx<R> (&acc)[RB][12]) {
+template <bool C12, int RB, typename SA, typename LA, typename R>
+__device__ __forceinline__ void outer_hops(const SA (&in)[RB], const LA& links, long V, int st, int dzp,
+                                           int dzm, bool y_fwd_out, int dyp, bool y_bwd_out, int dym,
+                                           cx<R> (&acc)[RB][12]) {
   hop_rb<2, -1, C12>(in, links, V, st + dzp, st, acc);
   hop_rb<2, +1, C12>(in, links, V, st + dzm, st + dzm, acc);
   if (y_fwd_out) hop_rb<1, -1, C12>(in, links, V, st + dyp, st, acc);
@@ -220,7 +277,7 @@ constexpr int march_waves_per_eu() {
   return RB == 1 && sizeof(typename Packed<T>::R) == 4 && CGM != kCgNone ? 3 : 1;
 }
 
-template <typename T, bool C12, int MAXT, int RB, int CGM>
+template <typename T, bool C12, int MAXT, int RB, int CGM, bool BUF>
 __global__ __launch_bounds__(MAXT)
 __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dslash_march_kernel(
     const typename Packed<T>::S* __restrict__ in, typename Packed<T>::S* __restrict__ out,
@@ -229,6 +286,7 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
   using R = typename Packed<T>::R;
   using SV = typename Packed<R>::S;
   using GS = typename Packed<T>::S;
+  static_assert(!BUF || CGM == kCgNone, "buffer-resource access only for the plain operator");
   constexpr int kPlanes = sizeof(R) == 8 ? 12 : 6;
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = geo.X * p.ny;  // sites per tile == lanes per lane group
@@ -245,15 +303,19 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
   // others. Further workgroups of the same tile are consecutive.
   const int groups = p.nrhs / (p.gw * RB);
   const int bb = tile_of_block(p.group);
-  const int rhs0 = ((bb % groups) * p.gw + slot) * RB;
+  // (with BUF the host launches one lane group per workgroup, so slot is 0 and
+  // the fields' bases derive from the block index alone: wave-uniform)
+  const int rhs0 = ((bb % groups) * p.gw + (BUF ? 0 : slot)) * RB;
   const int b = bb / groups;
-  const GS* inr[RB];
-  GS* outr[RB];
+  // the fields: plain pointers, or buffer resources (BUF)
+  decltype(field_in<BUF>(in, 0u)) inr[RB];
+  decltype(field_out<BUF>(out, 0u)) outr[RB];
+  const auto lk = field_in<BUF>(links, p.link_bytes);
   R diag[RB];
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
-    inr[r] = in + diags.idx[rhs0 + r] * stride;
-    outr[r] = out + diags.idx[rhs0 + r] * stride;
+    inr[r] = field_in<BUF>(in + diags.idx[rhs0 + r] * stride, p.spinor_bytes);
+    outr[r] = field_out<BUF>(out + diags.idx[rhs0 + r] * stride, p.spinor_bytes);
     diag[r] = diags.d[rhs0 + r];
   }
   const int yt = b % p.ytiles;
@@ -274,6 +336,11 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
   const int lym = (yl == 0 ? p.ny - 1 : yl - 1) * geo.X + xl;
   // site offsets of the periodic neighbours
   const int dxm = xl == 0 ? geo.X - 1 : -1;
+  // the lane holding x - 1, for the shuffled backward x link (x rows within a wave)
+  // (measured: FP32 storage 196 -> 192 us on 32^3x64; FP64 unchanged; with
+  // FP16 storage the 18 shuffles cost more than the 9 small loads they replace)
+  const bool xshfl = kXShfl && sizeof(T) == 4 && 64 % geo.X == 0;
+  const int src_lane = (static_cast<int>(threadIdx.x) & 63) + dxm;
   const int dyp = y + 1 == geo.Y ? -(geo.Y - 1) * geo.X : geo.X;
   const int dym = y == 0 ? (geo.Y - 1) * geo.X : -geo.X;
   const int dzp = z + 1 == geo.Z ? -(geo.Z - 1) * geo.XY : geo.XY;
@@ -320,8 +387,8 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
   {
     const int tm = t0 == 0 ? geo.T - 1 : t0 - 1;
     const int st = s0 + t0 * geo.XYZ;
-    outer_hops<C12>(inr, links, V, st, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, acc);
-    hop_rb<3, +1, C12>(inr, links, V, s0 + tm * geo.XYZ, s0 + tm * geo.XYZ, acc);
+    outer_hops<C12>(inr, lk, V, st, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, acc);
+    hop_rb<3, +1, C12>(inr, lk, V, s0 + tm * geo.XYZ, s0 + tm * geo.XYZ, acc);
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       cx<R> psi[12];
@@ -367,7 +434,7 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
     // U_t(t) serves the forward t hop of t and, from registers, the backward
     // t hop of t+1: no other workgroup reads it
     cx<R> ut[9];
-    load_link<C12, kUtNt>(links, V, 3, st, ut);
+    load_link<C12, kUtNt>(lk, V, 3, st, ut);
     cx<R> nacc[RB][12];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
@@ -379,7 +446,7 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
       load_spinor(inr[r], V, sn, psi);
       if (more) {
         lds_store_spinor(nxt[r], n, tid, psi);
-        if (r == 0) outer_hops<C12>(inr, links, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, nacc);
+        if (r == 0) outer_hops<C12>(inr, lk, V, sn, dzp, dzm, y_fwd_out, dyp, y_bwd_out, dym, nacc);
       }
       cx<R> h[6], g[6];
       project<3, -1>(psi, h);
@@ -387,10 +454,9 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
       reconstruct_add<3, -1>(g, acc[r]);
     }
     // x hops and in-tile y hops from LDS
-    lds_hop_rb<0, -1, C12>(cur, n, lxp, links, V, st, acc);
-    lds_hop_rb<0, +1, C12>(cur, n, lxm, links, V, st + dxm, acc);
-    if (!y_fwd_out) lds_hop_rb<1, -1, C12>(cur, n, lyp, links, V, st, acc);
-    if (!y_bwd_out) lds_hop_rb<1, +1, C12>(cur, n, lym, links, V, st + dym, acc);
+    lds_x_hops<C12>(cur, n, lxp, lxm, lk, V, st, dxm, xshfl, src_lane, acc);
+    if (!y_fwd_out) lds_hop_rb<1, -1, C12>(cur, n, lyp, lk, V, st, acc);
+    if (!y_bwd_out) lds_hop_rb<1, +1, C12>(cur, n, lym, lk, V, st + dym, acc);
     // epilogue of t; the backward t hop of t+1 joins the next accumulator
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
@@ -456,7 +522,7 @@ size_t march_lds_bytes(int threads, size_t real_bytes) {
 
 
 MarchParams march_params(const Geo& geo, size_t real_bytes, int nrhs) {
-  MarchParams p{0, 0, 0, 0, nrhs, 1, 1};
+  MarchParams p{0, 0, 0, 0, nrhs, 1, 1, 0u, 0u};
   if (geo.X > kMarchMaxThreads) return p;
   int ny = 0;
   for (int d = 1; d <= geo.Y; ++d)
@@ -505,7 +571,7 @@ MarchParams march_params(const Geo& geo, size_t real_bytes, int nrhs) {
   return p;
 }
 
-template <typename T, bool C12, int MAXT, int RB, int CGM>
+template <typename T, bool C12, int MAXT, int RB, int CGM, bool BUF>
 hipError_t launch_march_t(const void* in, void* out, const void* links, const Geo& geo,
                           const Diag<typename Packed<T>::R>& diag, long stride, int g5,
                           const MarchParams& p, const CgFuse& f, hipStream_t st) {
@@ -520,33 +586,46 @@ hipError_t launch_march_t(const void* in, void* out, const void* links, const Ge
   static std::atomic<int> attr_set{0};
   if (!attr_set.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&dslash_march_kernel<T, C12, MAXT, RB, CGM>),
+        reinterpret_cast<const void*>(&dslash_march_kernel<T, C12, MAXT, RB, CGM, BUF>),
         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
     if (e != hipSuccess) return e;
     attr_set.store(1, std::memory_order_release);
   }
   const unsigned nb = static_cast<unsigned>((p.nrhs / (p.gw * RB)) * p.ytiles * geo.Z *
                                             ((geo.T + p.tb - 1) / p.tb));
-  dslash_march_kernel<T, C12, MAXT, RB, CGM><<<nb, p.gw * n, lds, st>>>(
+  dslash_march_kernel<T, C12, MAXT, RB, CGM, BUF><<<nb, p.gw * n, lds, st>>>(
       static_cast<const SV*>(in), static_cast<SV*>(out), static_cast<const LV*>(links), geo, diag,
       stride, g5, p, f);
   return hipGetLastError();
 }
 
+template <typename T, bool C12, int CGM, bool BUF>
+hipError_t launch_march_b(const void* in, void* out, const void* links, const Geo& geo,
+                          const Diag<typename Packed<T>::R>& diag, long stride, int g5,
+                          const MarchParams& p, const CgFuse& f, hipStream_t st) {
+  if constexpr (sizeof(typename Packed<T>::R) == 4) {
+    if (p.rb == 2)  // two right-hand sides per lane: one lane group per workgroup
+      return launch_march_t<T, C12, kMarchMaxThreads, 2, CGM, BUF>(in, out, links, geo, diag, stride, g5,
+                                                                  p, f, st);
+    if (p.gw > 1)
+      return launch_march_t<T, C12, kMarchMultiThreads, 1, CGM, BUF>(in, out, links, geo, diag, stride,
+                                                                    g5, p, f, st);
+  }
+  return launch_march_t<T, C12, kMarchMaxThreads, 1, CGM, BUF>(in, out, links, geo, diag, stride, g5, p,
+                                                              f, st);
+}
+
+// The plain operator on FP64 and FP32 fields reads and writes them through
+// buffer resources when every field is below 4 GiB (WD_MARCH_BUF 0 turns it off).
 template <typename T, bool C12, int CGM>
 hipError_t launch_march(const void* in, void* out, const void* links, const Geo& geo,
                         const Diag<typename Packed<T>::R>& diag, long stride, int g5,
                         const MarchParams& p, const CgFuse& f, hipStream_t st) {
-  if constexpr (sizeof(typename Packed<T>::R) == 4) {
-    if (p.rb == 2)  // two right-hand sides per lane: one lane group per workgroup
-      return launch_march_t<T, C12, kMarchMaxThreads, 2, CGM>(in, out, links, geo, diag, stride, g5, p,
-                                                             f, st);
-    if (p.gw > 1)
-      return launch_march_t<T, C12, kMarchMultiThreads, 1, CGM>(in, out, links, geo, diag, stride, g5,
-                                                               p, f, st);
+  if constexpr (CGM == kCgNone && sizeof(T) >= 4) {
+    if (kMarchBuf && p.gw == 1 && p.link_bytes != 0 && p.spinor_bytes != 0)
+      return launch_march_b<T, C12, CGM, true>(in, out, links, geo, diag, stride, g5, p, f, st);
   }
-  return launch_march_t<T, C12, kMarchMaxThreads, 1, CGM>(in, out, links, geo, diag, stride, g5, p, f,
-                                                         st);
+  return launch_march_b<T, C12, CGM, false>(in, out, links, geo, diag, stride, g5, p, f, st);
 }
 
 template <typename T, bool C12>
@@ -586,6 +665,10 @@ hipError_t launch_typed(const wd_gauge* g, const void* in, void* out, const Geo&
   }
   const long stride = spinor_units<T>(geo.V);  // 16-B elements per field
   MarchParams p = march_params(geo, sizeof(R), nrhs);
+  // byte sizes for buffer-resource access, or 0 where a field reaches 4 GiB
+  const unsigned long sbytes = static_cast<unsigned long>(stride) * 16;
+  p.link_bytes = g->link_bytes < (1ul << 32) ? static_cast<unsigned>(g->link_bytes) : 0u;
+  p.spinor_bytes = sbytes < (1ul << 32) ? static_cast<unsigned>(sbytes) : 0u;
   if (WD_DSLASH_KERNEL == 0 && p.ny > 0) {
     MarchTuning t;
     if (force != nullptr) p = with_tuning(p, *force);

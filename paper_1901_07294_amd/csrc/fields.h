@@ -337,4 +337,124 @@ __device__ __forceinline__ void load_link(const h2* __restrict__ p, long V, int 
   }
 }
 
+// ------------------------------------------------ buffer-resource access
+//
+// FP64 and FP32 fields of less than 4 GiB can be read and written through a
+// raw buffer resource: the field's base (wave-uniform) sits in scalar
+// registers, every lane adds one 32-bit byte offset (its site's element in
+// plane 0) and every plane a scalar constant, so that no vector instruction
+// computes an address. With a 64-bit address per load the FP64 operator spent
+// about as many vector instructions on addresses as on arithmetic. Stores and
+// the non-temporal loads carry the non-temporal cache policy explicitly.
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename E>
+struct BufField {
+  __amdgpu_buffer_rsrc_t r;
+};
+
+constexpr int kBufWord3 = 0x00020000;  // descriptor word 3: raw dword access (gfx9 family)
+constexpr int kBufNt = 2;              // cache policy: non-temporal
+constexpr int kPlane16 = kLayoutBlock * 16;  // bytes between planes of 16-byte elements
+
+template <typename E>
+__device__ __forceinline__ BufField<E> buf_field(const E* p, unsigned bytes) {
+  return {__builtin_amdgcn_make_buffer_rsrc(const_cast<E*>(p), static_cast<short>(0),
+                                            static_cast<int>(bytes), kBufWord3)};
+}
+
+// Byte offset of site s's element of plane 0 in a field of P planes of
+// ES-byte elements (the caller guarantees the field is below 4 GiB).
+template <int P, int ES>
+__device__ __forceinline__ unsigned site_off(int s) {
+  const unsigned u = static_cast<unsigned>(s);
+  return ((u / kLayoutBlock) * (P * kLayoutBlock) + (u % kLayoutBlock)) * ES;
+}
+
+template <int POL = 0>
+__device__ __forceinline__ nd2 buf_ld2(const BufField<double2>& f, unsigned o, int so) {
+  return __builtin_bit_cast(nd2, __builtin_amdgcn_raw_buffer_load_b128(f.r, o, so, POL));
+}
+
+__device__ __forceinline__ void load_spinor(const BufField<double2>& f, long /*V*/, int s,
+                                            cx<double> (&v)[12]) {
+  const unsigned o = site_off<12, 16>(s);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const nd2 t = buf_ld2(f, o, c * kPlane16);
+    v[c] = {t.x, t.y};
+  }
+}
+
+__device__ __forceinline__ void load_spinor(const BufField<float4>& f, long /*V*/, int s,
+                                            cx<float> (&v)[12]) {
+  const unsigned o = site_off<6, 16>(s);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const nf4 t = __builtin_bit_cast(nf4, __builtin_amdgcn_raw_buffer_load_b128(f.r, o, j * kPlane16, 0));
+    v[2 * j] = {t.x, t.y};
+    v[2 * j + 1] = {t.z, t.w};
+  }
+}
+
+__device__ __forceinline__ void store_spinor(const BufField<double2>& f, long /*V*/, int s,
+                                             const cx<double> (&v)[12]) {
+  const unsigned o = site_off<12, 16>(s);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const nd2 t = {v[c].re, v[c].im};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t), f.r, o, c * kPlane16, kBufNt);
+  }
+}
+
+__device__ __forceinline__ void store_spinor(const BufField<float4>& f, long /*V*/, int s,
+                                             const cx<float> (&v)[12]) {
+  const unsigned o = site_off<6, 16>(s);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const nf4 t = {v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t), f.r, o, j * kPlane16, kBufNt);
+  }
+}
+
+template <bool C12, bool NT = false>
+__device__ __forceinline__ void load_link(const BufField<double2>& f, long /*V*/, int mu, int s,
+                                          cx<double> (&u)[9]) {
+  constexpr int n = C12 ? 6 : 9;
+  const unsigned o = site_off<4 * n, 16>(s);
+#pragma unroll
+  for (int k = 0; k < n; ++k) {
+    const nd2 t = buf_ld2<NT ? kBufNt : 0>(f, o, (mu * n + k) * kPlane16);
+    u[k] = {t.x, t.y};
+  }
+  if constexpr (C12) rebuild_row2(u);
+}
+
+template <bool C12, bool NT = false>
+__device__ __forceinline__ void load_link(const BufField<float2>& f, long /*V*/, int mu, int s,
+                                          cx<float> (&u)[9]) {
+  constexpr int pol = NT ? kBufNt : 0;
+  if constexpr (C12) {
+    const unsigned o = site_off<12, 16>(s);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const nf4 t = __builtin_bit_cast(
+          nf4, __builtin_amdgcn_raw_buffer_load_b128(f.r, o, (mu * 3 + j) * kPlane16, pol));
+      u[2 * j] = {t.x, t.y};
+      u[2 * j + 1] = {t.z, t.w};
+    }
+    rebuild_row2(u);
+  } else {
+    const unsigned o = site_off<36, 8>(s);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const nf2 t = __builtin_bit_cast(
+          nf2, __builtin_amdgcn_raw_buffer_load_b64(f.r, o, (mu * 9 + k) * kLayoutBlock * 8, pol));
+      u[k] = {t.x, t.y};
+    }
+  }
+}
+
 }  // namespace wd
