@@ -286,7 +286,6 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
   using R = typename Packed<T>::R;
   using SV = typename Packed<R>::S;
   using GS = typename Packed<T>::S;
-  static_assert(!BUF || CGM == kCgNone, "buffer-resource access only for the plain operator");
   constexpr int kPlanes = sizeof(R) == 8 ? 12 : 6;
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = geo.X * p.ny;  // sites per tile == lanes per lane group
@@ -307,15 +306,17 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
   // the fields' bases derive from the block index alone: wave-uniform)
   const int rhs0 = ((bb % groups) * p.gw + (BUF ? 0 : slot)) * RB;
   const int b = bb / groups;
-  // the fields: plain pointers, or buffer resources (BUF)
+  // the fields: plain pointers, or buffer resources (BUF; the fused CG work
+  // writes its outputs through plain pointers)
+  constexpr bool kBufOut = BUF && CGM == kCgNone;
   decltype(field_in<BUF>(in, 0u)) inr[RB];
-  decltype(field_out<BUF>(out, 0u)) outr[RB];
+  decltype(field_out<kBufOut>(out, 0u)) outr[RB];
   const auto lk = field_in<BUF>(links, p.link_bytes);
   R diag[RB];
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
     inr[r] = field_in<BUF>(in + diags.idx[rhs0 + r] * stride, p.spinor_bytes);
-    outr[r] = field_out<BUF>(out + diags.idx[rhs0 + r] * stride, p.spinor_bytes);
+    outr[r] = field_out<kBufOut>(out + diags.idx[rhs0 + r] * stride, p.spinor_bytes);
     diag[r] = diags.d[rhs0 + r];
   }
   const int yt = b % p.ytiles;
@@ -339,7 +340,7 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
   // the lane holding x - 1, for the shuffled backward x link (x rows within a wave)
   // (measured: FP32 storage 196 -> 192 us on 32^3x64; FP64 unchanged; with
   // FP16 storage the 18 shuffles cost more than the 9 small loads they replace)
-  const bool xshfl = kXShfl && sizeof(T) == 4 && 64 % geo.X == 0;
+  const bool xshfl = kXShfl && sizeof(T) == 4 && RB == 1 && CGM == kCgNone && 64 % geo.X == 0;
   const int src_lane = (static_cast<int>(threadIdx.x) & 63) + dxm;
   const int dyp = y + 1 == geo.Y ? -(geo.Y - 1) * geo.X : geo.X;
   const int dym = y == 0 ? (geo.Y - 1) * geo.X : -geo.X;
@@ -473,6 +474,11 @@ __attribute__((amdgpu_waves_per_eu(march_waves_per_eu<CGM, T, RB>()))) void dsla
         double v = store_site_norm(outr[r], V, st, o);
         v = wave_total(v);
         if ((tid & 63) == 0) cgs[r * kCgLds + 4 * ((t - t0) & 1) + (tid >> 6)] = v;
+      } else if constexpr (kBufOut && sizeof(R) == 8 && !C12) {
+        // FP64 with full links stores with the default cache policy (measured
+        // 360.4 -> 358.9 us on 32^3x64; with 12-real links and in FP32 the
+        // non-temporal stores are faster)
+        store_spinor<0>(outr[r], V, st, o);
       } else {
         store_spinor(outr[r], V, st, o);
       }
@@ -615,16 +621,15 @@ hipError_t launch_march_b(const void* in, void* out, const void* links, const Ge
                                                               f, st);
 }
 
-// The plain operator on FP64 and FP32 fields reads and writes them through
-// buffer resources when every field is below 4 GiB (WD_MARCH_BUF 0 turns it off).
+// The operator reads its fields (and the plain operator also writes them)
+// through buffer resources when every field is below 4 GiB and a workgroup
+// holds one lane group (WD_MARCH_BUF 0 turns it off).
 template <typename T, bool C12, int CGM>
 hipError_t launch_march(const void* in, void* out, const void* links, const Geo& geo,
                         const Diag<typename Packed<T>::R>& diag, long stride, int g5,
                         const MarchParams& p, const CgFuse& f, hipStream_t st) {
-  if constexpr (CGM == kCgNone && sizeof(T) >= 4) {
-    if (kMarchBuf && p.gw == 1 && p.link_bytes != 0 && p.spinor_bytes != 0)
-      return launch_march_b<T, C12, CGM, true>(in, out, links, geo, diag, stride, g5, p, f, st);
-  }
+  if (kMarchBuf && p.gw == 1 && p.link_bytes != 0 && p.spinor_bytes != 0)
+    return launch_march_b<T, C12, CGM, true>(in, out, links, geo, diag, stride, g5, p, f, st);
   return launch_march_b<T, C12, CGM, false>(in, out, links, geo, diag, stride, g5, p, f, st);
 }
 

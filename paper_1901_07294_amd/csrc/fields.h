@@ -399,13 +399,15 @@ __device__ __forceinline__ void load_spinor(const BufField<float4>& f, long /*V*
   }
 }
 
+// POL: the stores' cache policy (non-temporal by default)
+template <int POL = kBufNt>
 __device__ __forceinline__ void store_spinor(const BufField<double2>& f, long /*V*/, int s,
                                              const cx<double> (&v)[12]) {
   const unsigned o = site_off<12, 16>(s);
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
     const nd2 t = {v[c].re, v[c].im};
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t), f.r, o, c * kPlane16, kBufNt);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t), f.r, o, c * kPlane16, POL);
   }
 }
 
@@ -453,6 +455,68 @@ __device__ __forceinline__ void load_link(const BufField<float2>& f, long /*V*/,
       const nf2 t = __builtin_bit_cast(
           nf2, __builtin_amdgcn_raw_buffer_load_b64(f.r, o, (mu * 9 + k) * kLayoutBlock * 8, pol));
       u[k] = {t.x, t.y};
+    }
+  }
+}
+
+// FP16 storage (64-site blocks): a spinor block is 3 planes of 64 x 16 bytes
+// followed by 64 FP32 scales; links are planes of 64 x 4 bytes (full) or
+// 64 x 8 bytes (12-real).
+__device__ __forceinline__ unsigned half_block_off(int s) {
+  return (static_cast<unsigned>(s) / kHalfBlock) * (Packed<_Float16>::kBlockUnits * 16u);
+}
+
+__device__ __forceinline__ void load_spinor(const BufField<h8>& f, long /*V*/, int s, cx<float> (&v)[12]) {
+  const unsigned b = half_block_off(s);
+  const unsigned l = static_cast<unsigned>(s) % kHalfBlock;
+  const float sc = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                 f.r, b + 3 * kHalfBlock * 16 + l * 4, 0, 0));
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const h8 t = __builtin_bit_cast(h8, __builtin_amdgcn_raw_buffer_load_b128(f.r, b + l * 16, j * kHalfBlock * 16, 0));
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      v[4 * j + k] = {fmar(static_cast<float>(t[2 * k]), sc, 0.0f),
+                      fmar(static_cast<float>(t[2 * k + 1]), sc, 0.0f)};
+  }
+}
+
+__device__ __forceinline__ void store_spinor(const BufField<h8>& f, long /*V*/, int s,
+                                             const cx<float> (&v)[12]) {
+  h8 q[3];
+  const float m = half_quantise(v, q);
+  const unsigned b = half_block_off(s);
+  const unsigned l = static_cast<unsigned>(s) % kHalfBlock;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, q[j]), f.r, b + l * 16, j * kHalfBlock * 16,
+                                           kBufNt);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, m), f.r, b + 3 * kHalfBlock * 16 + l * 4, 0,
+                                        kBufNt);
+}
+
+template <bool C12, bool NT = false>
+__device__ __forceinline__ void load_link(const BufField<h2>& f, long /*V*/, int mu, int s, cx<float> (&u)[9]) {
+  constexpr int pol = NT ? kBufNt : 0;
+  const unsigned blk = static_cast<unsigned>(s) / kHalfBlock;
+  const unsigned l = static_cast<unsigned>(s) % kHalfBlock;
+  if constexpr (C12) {
+    const unsigned o = blk * (12 * kHalfBlock * 8) + l * 8;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const h4 t = __builtin_bit_cast(
+          h4, __builtin_amdgcn_raw_buffer_load_b64(f.r, o, (mu * 3 + j) * kHalfBlock * 8, pol));
+      u[2 * j] = {static_cast<float>(t.x), static_cast<float>(t.y)};
+      u[2 * j + 1] = {static_cast<float>(t.z), static_cast<float>(t.w)};
+    }
+    rebuild_row2(u);
+  } else {
+    const unsigned o = blk * (36 * kHalfBlock * 4) + l * 4;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const h2 t = __builtin_bit_cast(
+          h2, __builtin_amdgcn_raw_buffer_load_b32(f.r, o, (mu * 9 + k) * kHalfBlock * 4, pol));
+      u[k] = {static_cast<float>(t.x), static_cast<float>(t.y)};
     }
   }
 }
