@@ -27,6 +27,7 @@ enum : int {
   kB2 = 6,      // <b, b>
   kFlag = 7,    // nonzero: a non-finite or non-positive quantity appeared
   kRrPrev = 8,  // <r, r> before the current x, r update (beta's denominator)
+  kAlphaPrev = 9,  // alpha of an x update left for the next iteration (blas_update_xp_lo)
   kScalars = 10  // even: the scalars are cleared as 16-byte elements
 };
 
@@ -64,9 +65,17 @@ hipError_t blas_update_xp(void* x, void* p, const void* r, long n, const RhsSet&
 // applied r -= alpha Ap in its epilogue: x_lo += alpha p (alpha as that launch
 // recorded it; x_lo the FP32 accumulator, nlo32 16-byte elements per
 // right-hand side), then p = r + beta p with beta reduced from the nrr <r,r>
-// partial sums in rr; p is read once.
-hipError_t blas_update_xp_lo(void* x, void* p, const void* r, int prec, long n, long nlo32, long V,
-                             const RhsSet& set, const double* rr, int nrr, double* scal, hipStream_t st);
+// partial sums in rr; p is read once. kind:
+//   kXpNow:   x_lo += alpha p_cur; p_out = r + beta p_cur (p_out may be p_cur)
+//   kXpDefer: p_out = r + beta p_cur into another buffer, x_lo left alone and
+//             alpha kept (kAlphaPrev) for the next call
+//   kXpPair:  x_lo += alpha_prev p_prev, then += alpha p_cur (the two updates
+//             of kXpNow calls in turn, bit for bit); p_out = r + beta p_cur
+//             (p_out may be p_prev)
+enum : int { kXpNow = 0, kXpDefer = 1, kXpPair = 2 };
+hipError_t blas_update_xp_lo(void* x, void* p_out, const void* p_cur, const void* p_prev, const void* r,
+                             int kind, int prec, long n, long nlo32, long V, const RhsSet& set,
+                             const double* rr, int nrr, double* scal, hipStream_t st);
 // x_hi += x_lo, then x_lo = 0
 hipError_t blas_flush_x(void* hi, void* lo, long nlo32, long nhi, const RhsSet& set, hipStream_t st);
 // p = r + beta p with beta = <r,r>_new / <r,r>_old, <r,r>_new reduced from the

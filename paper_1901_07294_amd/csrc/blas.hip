@@ -252,34 +252,50 @@ __global__ __launch_bounds__(kThreads) void update_xp_kernel(double2* __restrict
 // r -= alpha Ap in its epilogue: x_lo += alpha p, then p = r + beta p, with
 // alpha as that launch recorded it (the value all its workgroups applied) and
 // beta reduced from its <r,r> per tile slice. The multiply-adds are those of
-// update_xr_kernel and update_p_kernel, so the bits match.
-__global__ __launch_bounds__(kThreads) void update_xp_lo_kernel(float4* __restrict__ x,
-                                                                float4* __restrict__ p,
+// update_xr_kernel and update_p_kernel, so the bits match. KIND (blas.h):
+// which x update is applied; p_out is written after p_cur and p_prev are
+// read, by the same lane, so it may be either of them.
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void update_xp_lo_kernel(float4* __restrict__ x, float4* p_out,
+                                                                const float4* p_cur, const float4* p_prev,
                                                                 const float4* __restrict__ r, long n,
                                                                 RhsSet set, const double* __restrict__ rr,
                                                                 int nrr, double* __restrict__ scal) {
   const int k = set.idx[blockIdx.y];
   double* sc = scal + k * kScalars;
   const float a = static_cast<float>(sc[kAlpha]);  // not written by this kernel
+  const float a0 = KIND == kXpPair ? static_cast<float>(sc[kAlphaPrev]) : 0.0f;
+  if (KIND == kXpDefer && blockIdx.x == 0 && threadIdx.x == 0) sc[kAlphaPrev] = sc[kAlpha];
   const float b = static_cast<float>(beta_from_partials(rr + k * nrr, nrr, sc));
   float4* xk = x + k * n;
-  float4* pk = p + k * n;
+  float4* pok = p_out + k * n;
+  const float4* pck = p_cur + k * n;
+  const float4* ppk = p_prev + k * n;
   const float4* rk = r + k * n;
   for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
        e += static_cast<long>(gridDim.x) * kThreads) {
-    float4 pe = pk[e];
+    float4 pe = pck[e];
     const float4 re = rk[e];
-    float4 xe = xk[e];
-    xe.x = fmar(a, pe.x, xe.x);
-    xe.y = fmar(a, pe.y, xe.y);
-    xe.z = fmar(a, pe.z, xe.z);
-    xe.w = fmar(a, pe.w, xe.w);
+    if constexpr (KIND != kXpDefer) {
+      float4 xe = xk[e];
+      if constexpr (KIND == kXpPair) {
+        const float4 q = ppk[e];
+        xe.x = fmar(a0, q.x, xe.x);
+        xe.y = fmar(a0, q.y, xe.y);
+        xe.z = fmar(a0, q.z, xe.z);
+        xe.w = fmar(a0, q.w, xe.w);
+      }
+      xe.x = fmar(a, pe.x, xe.x);
+      xe.y = fmar(a, pe.y, xe.y);
+      xe.z = fmar(a, pe.z, xe.z);
+      xe.w = fmar(a, pe.w, xe.w);
+      xk[e] = xe;
+    }
     pe.x = fmar(b, pe.x, re.x);
     pe.y = fmar(b, pe.y, re.y);
     pe.z = fmar(b, pe.z, re.z);
     pe.w = fmar(b, pe.w, re.w);
-    xk[e] = xe;
-    pk[e] = pe;
+    pok[e] = pe;
   }
 }
 
@@ -442,8 +458,11 @@ __global__ __launch_bounds__(kThreads) void update_xr_half_kernel(
 
 // Mixed precision, FP16-storage vectors, after the dslash launch that applied
 // r -= alpha Ap: x_lo += alpha p (x_lo FP32, nlo32 elements per right-hand
-// side), then p = r + beta p requantised; alpha and beta as update_xp_lo_kernel.
-__global__ __launch_bounds__(kThreads) void update_xp_half_kernel(float4* __restrict__ x, h8* __restrict__ p,
+// side), then p = r + beta p requantised; alpha, beta, KIND and the buffers
+// as update_xp_lo_kernel.
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void update_xp_half_kernel(float4* __restrict__ x, h8* p_out,
+                                                                  const h8* p_cur, const h8* p_prev,
                                                                   const h8* __restrict__ r, long units,
                                                                   long nlo32, long V, RhsSet set,
                                                                   const double* __restrict__ rr, int nrr,
@@ -451,18 +470,28 @@ __global__ __launch_bounds__(kThreads) void update_xp_half_kernel(float4* __rest
   const int k = set.idx[blockIdx.y];
   double* sc = scal + k * kScalars;
   const float a = static_cast<float>(sc[kAlpha]);  // not written by this kernel
+  const float a0 = KIND == kXpPair ? static_cast<float>(sc[kAlphaPrev]) : 0.0f;
+  if (KIND == kXpDefer && blockIdx.x == 0 && threadIdx.x == 0) sc[kAlphaPrev] = sc[kAlpha];
   const float b = static_cast<float>(beta_from_partials(rr + k * nrr, nrr, sc));
   float4* xk = x + k * nlo32;
-  h8* pk = p + k * units;
+  h8* pok = p_out + k * units;
+  const h8* pck = p_cur + k * units;
+  const h8* ppk = p_prev + k * units;
   const h8* rk = r + k * units;
   WD_SITE_LOOP(i, V) {
     cx<float> pv[12], rv[12];
-    load_spinor(pk, V, static_cast<int>(i), pv);
-    cg_site_update_x(xk, V, i, pv, a);
+    load_spinor(pck, V, static_cast<int>(i), pv);
+    if constexpr (KIND == kXpPair) {
+      cx<float> qv[12];
+      load_spinor(ppk, V, static_cast<int>(i), qv);
+      cg_site_update_x2(xk, V, i, qv, a0, pv, a);
+    } else if constexpr (KIND == kXpNow) {
+      cg_site_update_x(xk, V, i, pv, a);
+    }
     load_spinor(rk, V, static_cast<int>(i), rv);
 #pragma unroll
     for (int c = 0; c < 12; ++c) pv[c] = {fmar(b, pv[c].re, rv[c].re), fmar(b, pv[c].im, rv[c].im)};
-    store_half_site(pk, i, pv);
+    store_half_site(pok, i, pv);
   }
 }
 
@@ -628,18 +657,40 @@ hipError_t blas_update_p(void* p, const void* r, int prec, long n, long V, const
   return hipGetLastError();
 }
 
-hipError_t blas_update_xp_lo(void* x, void* p, const void* r, int prec, long n, long nlo32, long V,
-                             const RhsSet& set, const double* rr, int nrr, double* scal, hipStream_t st) {
-  if (prec == WD_FP32)
-    update_xp_lo_kernel<<<grid(n, set.n), kThreads, 0, st>>>(static_cast<float4*>(x), static_cast<float4*>(p),
-                                                             static_cast<const float4*>(r), n, set, rr, nrr,
-                                                             scal);
-  else if (prec == WD_FP16)
-    update_xp_half_kernel<<<grid(V, set.n), kThreads, 0, st>>>(static_cast<float4*>(x), static_cast<h8*>(p),
-                                                               static_cast<const h8*>(r), n, nlo32, V, set,
-                                                               rr, nrr, scal);
-  else
+hipError_t blas_update_xp_lo(void* x, void* p_out, const void* p_cur, const void* p_prev, const void* r,
+                             int kind, int prec, long n, long nlo32, long V, const RhsSet& set,
+                             const double* rr, int nrr, double* scal, hipStream_t st) {
+  if (kind != kXpNow && kind != kXpDefer && kind != kXpPair) return hipErrorInvalidValue;
+  if (kind == kXpDefer && p_out == p_cur) return hipErrorInvalidValue;
+  if (prec == WD_FP32) {
+    auto* xo = static_cast<float4*>(x);
+    auto* po = static_cast<float4*>(p_out);
+    auto* pc = static_cast<const float4*>(p_cur);
+    auto* pp = static_cast<const float4*>(p_prev);
+    auto* rv = static_cast<const float4*>(r);
+    const dim3 g = grid(n, set.n);
+    if (kind == kXpNow) update_xp_lo_kernel<kXpNow><<<g, kThreads, 0, st>>>(xo, po, pc, pp, rv, n, set, rr, nrr, scal);
+    else if (kind == kXpDefer)
+      update_xp_lo_kernel<kXpDefer><<<g, kThreads, 0, st>>>(xo, po, pc, pp, rv, n, set, rr, nrr, scal);
+    else update_xp_lo_kernel<kXpPair><<<g, kThreads, 0, st>>>(xo, po, pc, pp, rv, n, set, rr, nrr, scal);
+  } else if (prec == WD_FP16) {
+    auto* xo = static_cast<float4*>(x);
+    auto* po = static_cast<h8*>(p_out);
+    auto* pc = static_cast<const h8*>(p_cur);
+    auto* pp = static_cast<const h8*>(p_prev);
+    auto* rv = static_cast<const h8*>(r);
+    const dim3 g = grid(V, set.n);
+    if (kind == kXpNow)
+      update_xp_half_kernel<kXpNow><<<g, kThreads, 0, st>>>(xo, po, pc, pp, rv, n, nlo32, V, set, rr, nrr, scal);
+    else if (kind == kXpDefer)
+      update_xp_half_kernel<kXpDefer><<<g, kThreads, 0, st>>>(xo, po, pc, pp, rv, n, nlo32, V, set, rr, nrr,
+                                                               scal);
+    else
+      update_xp_half_kernel<kXpPair><<<g, kThreads, 0, st>>>(xo, po, pc, pp, rv, n, nlo32, V, set, rr, nrr,
+                                                              scal);
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

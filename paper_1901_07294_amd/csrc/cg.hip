@@ -58,6 +58,11 @@ CgLayout cg_layout(const int32_t dims[4], int slots, int inner, bool eo) {
   }
   w.r = o; o += lo;
   w.p = o; o += lo;
+  w.p2 = w.p;
+  if (w.nslices > 0 && inner != WD_FP64) {  // the direction of an iteration whose x update waits
+    w.p2 = o;
+    o += lo;
+  }
   w.t = o; o += lo;
   if (w.nslices == 0 || inner == WD_FP64) {  // FP64 keeps A p (the update is not fused)
     w.ap = o;
@@ -151,7 +156,13 @@ int CgEngine::start(const RhsSet& set, bool x0_given) {
   return launch_status(blas_copy(at(ws_, lay_.p), at(ws_, lay_.r), inner_, nlo_, set, st_), "cg: p0");
 }
 
-int CgEngine::iterate(const RhsSet& set) {
+int CgEngine::chunk(const RhsSet& set, int n) {
+  int rc = WD_OK;
+  for (int j = 0; j < n && rc == WD_OK; ++j) rc = iterate(set, j, n);
+  return rc;
+}
+
+int CgEngine::iterate(const RhsSet& set, int j, int n) {
   double m[kMaxRhs];
   for (int i = 0; i < set.n; ++i) m[i] = masses_[set.idx[i]];
   if (lay_.nslices > 0 && inner_ == WD_FP64) {
@@ -180,13 +191,21 @@ int CgEngine::iterate(const RhsSet& set) {
     // t = Q p, with <p, A p> = |t|^2 summed per tile slice in the same launch;
     // then Q t = A p used at once for r -= alpha A p, with <r, r> per tile
     // slice (A p is never stored); then x += alpha p and p = r + beta p
-    // together (p is read once)
+    // together (p is read once). In iteration j = 0, 2, ... of the chunk,
+    // unless it is the last, p moves to p2 and x += alpha p waits for
+    // iteration j + 1, which adds both directions' terms and moves p back
+    // (x_lo is read and written once per two iterations).
+    void* const p1 = at(ws_, lay_.p);
+    void* const p2 = at(ws_, lay_.p2);
+    const bool second = (j & 1) != 0;
+    const int kind = second ? kXpPair : (j + 1 < n ? kXpDefer : kXpNow);
+    void* const pc = second ? p2 : p1;
     CgFuse f{};
     f.mode = kCgNorm;
     f.rr = paps_;
     f.nslices = lay_.nslices;
-    int rc = launch_status(launch_dslash_cg(glo_, m, set.n, set.idx, at(ws_, lay_.p), at(ws_, lay_.t), f,
-                                            st_), "cg: Q p with |Q p|^2");
+    int rc = launch_status(launch_dslash_cg(glo_, m, set.n, set.idx, pc, at(ws_, lay_.t), f, st_),
+                           "cg: Q p with |Q p|^2");
     f.mode = kCgUpdate;
     f.r = at(ws_, lay_.r);
     f.pap = paps_;
@@ -197,8 +216,9 @@ int CgEngine::iterate(const RhsSet& set) {
       rc = launch_status(launch_dslash_cg(glo_, m, set.n, set.idx, at(ws_, lay_.t), nullptr, f, st_),
                          "cg: Q Q p with r");
     if (rc == WD_OK)
-      rc = launch_status(blas_update_xp_lo(at(ws_, lay_.x_lo), at(ws_, lay_.p), at(ws_, lay_.r), inner_,
-                                           nlo_, n32_, V_, set, rr_, lay_.nslices, scal_, st_),
+      rc = launch_status(blas_update_xp_lo(at(ws_, lay_.x_lo), kind == kXpDefer ? p2 : p1, pc, p1,
+                                           at(ws_, lay_.r), kind, inner_, nlo_, n32_, V_, set, rr_,
+                                           lay_.nslices, scal_, st_),
                          "cg: x, p");
     return rc;
   }
@@ -279,8 +299,7 @@ class ChunkGraphs {
     if (it == execs_.end()) {
       hipError_t e = hipStreamBeginCapture(st_, hipStreamCaptureModeRelaxed);
       if (e != hipSuccess) return set_error(WD_ERR_DEVICE, "cg: graph capture: %s", hipGetErrorString(e));
-      int rc = WD_OK;
-      for (int i = 0; i < n && rc == WD_OK; ++i) rc = eng.iterate(set);
+      const int rc = eng.chunk(set, n);
       hipGraph_t graph = nullptr;
       e = hipStreamEndCapture(st_, &graph);
       hipGraphExec_t exec = nullptr;
@@ -465,11 +484,7 @@ int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, i
     // iterations up to the next check (a multiple of check_every, or max_iter)
     const int n = std::min(prm.check_every - it % prm.check_every, prm.max_iter - it);
     const RhsSet set = active.set();
-    if (graphs) {
-      rc = graphs->run(eng, set, n);
-    } else {
-      for (int i = 0; i < n && rc == WD_OK; ++i) rc = eng.iterate(set);
-    }
+    rc = graphs ? graphs->run(eng, set, n) : eng.chunk(set, n);
     if (rc != WD_OK) break;
     it += n;
     for (int i = 0; i < active.n; ++i) iters[active.k[i]] = it;

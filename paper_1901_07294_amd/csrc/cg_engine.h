@@ -12,14 +12,16 @@ namespace wd {
 // Offsets (bytes) of a CG workspace for `slots` right-hand sides. Where the
 // iteration's vector work is fused into its applications of Q (nslices > 0),
 // paps and rr hold the |Q p|^2 and <r,r> partial sums of the tile slices, and
-// (FP32 arithmetic, where the update is fused too) A p is never stored.
+// (FP32 arithmetic, where the update is fused too) A p is never stored, and p
+// and p2 hold the search directions of two consecutive iterations (the x
+// update of one iteration waits for the next, see CgEngine::chunk).
 // With eo (an even-odd gauge field) the vectors are odd half fields of V/2
 // sites, A = (gamma5 S)^2 with the odd-site Schur complement S, and e_lo /
 // e_hi are the even half fields each application of gamma5 S passes through.
 struct CgLayout {
   size_t bytes = 0;
-  size_t r_hi = 0, t_hi = 0, x_lo = 0, r = 0, p = 0, t = 0, ap = 0, partials = 0, pap = 0, scal = 0,
-         rr = 0, paps = 0, e_lo = 0, e_hi = 0;
+  size_t r_hi = 0, t_hi = 0, x_lo = 0, r = 0, p = 0, p2 = 0, t = 0, ap = 0, partials = 0, pap = 0,
+         scal = 0, rr = 0, paps = 0, e_lo = 0, e_hi = 0;
   int nslices = 0;
 };
 CgLayout cg_layout(const int32_t dims[4], int slots, int inner, bool eo = false);
@@ -51,8 +53,13 @@ class CgEngine {
   // scalars of the slots zeroed, <b,b>, x = 0 and r = b (or r = b - A x
   // when x0_given), inner residual and p = r.
   int start(const RhsSet& set, bool x0_given);
-  // one CG iteration on the slots of set
-  int iterate(const RhsSet& set);
+  // n CG iterations on the slots of set. Where the inner vector updates are
+  // fused (FP32 arithmetic), the x update of an even-numbered iteration of
+  // the chunk (0, 2, ...) that is not the last is left for the next one,
+  // which applies both in turn (the same operations in the same order), with
+  // that iteration's p kept in p2 meanwhile; a chunk ends with x and p
+  // complete and p in its own buffer.
+  int chunk(const RhsSet& set, int n);
   // (mixed precision: x += x_lo, x_lo = 0) FP64 true residual r = b - A x;
   // inner residual restarted from it
   int refresh(const RhsSet& set);
@@ -61,6 +68,8 @@ class CgEngine {
   int fetch_scalars(double* host) const;
 
  private:
+  // iteration j of a chunk of n
+  int iterate(const RhsSet& set, int j, int n);
   // out = Q in (Q = gamma5 D, or gamma5 S through the even fields tmp)
   int apply_q(const wd_gauge* g, const double* m, const RhsSet& set, const void* in, void* tmp, void* out,
               const char* what) const;

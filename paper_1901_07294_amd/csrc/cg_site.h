@@ -91,6 +91,27 @@ __device__ __forceinline__ void cg_site_update_x(float4* __restrict__ x, long V,
   }
 }
 
+// x_lo += a0 p0, then += a1 p1, at one site (two updates of
+// cg_site_update_x in turn, with one read and one write of x_lo).
+__device__ __forceinline__ void cg_site_update_x2(float4* __restrict__ x, long V, long s,
+                                                  const cx<float> (&p0)[12], float a0,
+                                                  const cx<float> (&p1)[12], float a1) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const long e = pidx(s, j, 6, V);
+    float4 xe = x[e];
+    xe.x = fmar(a0, p0[2 * j].re, xe.x);
+    xe.y = fmar(a0, p0[2 * j].im, xe.y);
+    xe.z = fmar(a0, p0[2 * j + 1].re, xe.z);
+    xe.w = fmar(a0, p0[2 * j + 1].im, xe.w);
+    xe.x = fmar(a1, p1[2 * j].re, xe.x);
+    xe.y = fmar(a1, p1[2 * j].im, xe.y);
+    xe.z = fmar(a1, p1[2 * j + 1].re, xe.z);
+    xe.w = fmar(a1, p1[2 * j + 1].im, xe.w);
+    x[e] = xe;
+  }
+}
+
 // FP16-storage vectors: x is the FP32 accumulator x_lo (FP32 layout); r is
 // requantised per site.
 __device__ __forceinline__ double cg_site_update(float4* __restrict__ x, h8* __restrict__ r,

@@ -679,7 +679,13 @@ hipError_t launch_typed(const wd_gauge* g, const void* in, void* out, const Geo&
     if (force != nullptr) p = with_tuning(p, *force);
     else if (tuned_lookup(g->dims, g->prec, g->c12, nrhs, &t)) p = with_tuning(p, t);
     if (cg != nullptr) {
-      if ((geo.X * p.ny) % 64 != 0) return hipErrorInvalidValue;
+      // whole waves per tile, a partial sum slot for every tile slice, and the
+      // inputs the update reads
+      if ((geo.X * p.ny) % 64 != 0 || cg->rr == nullptr ||
+          static_cast<long>(cg->nslices) < static_cast<long>(geo.T) * geo.Z * p.ytiles)
+        return hipErrorInvalidValue;
+      if (cg->mode == kCgUpdate && (cg->r == nullptr || cg->pap == nullptr || cg->npap < 1 || cg->scal == nullptr))
+        return hipErrorInvalidValue;
       if (cg->mode == kCgNorm)
         return launch_march<T, C12, kCgNorm>(in, out, g->links, geo, diag, stride, g5, p, *cg, st);
       if constexpr (sizeof(R) == 4) {  // the update is fused with FP32 arithmetic only

@@ -258,8 +258,7 @@ void wd_server::launch_chunk(Group& g) {
   for (int k = 0; k < g.S; ++k)
     if (g.slots[k].req != nullptr) ks.push_back(k);
   const RhsSet set = set_of(ks);
-  for (int i = 0; i < cfg.check_every; ++i)
-    if (g.eng->iterate(set) != WD_OK) fatal = WD_ERR_DEVICE;
+  if (g.eng->chunk(set, cfg.check_every) != WD_OK) fatal = WD_ERR_DEVICE;
   for (int k : ks) g.slots[k].iters += cfg.check_every;
   if (g.eng->fetch_scalars(g.host_scal) != WD_OK || hipEventRecord(g.ev, g.stream) != hipSuccess)
     fatal = WD_ERR_DEVICE;

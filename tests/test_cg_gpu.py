@@ -100,6 +100,31 @@ def test_cg_24_4_near_unity(inner):
     print(stats[0])
 
 
+@pytest.mark.parametrize("inner", ["fp32", "fp16"])
+def test_cg_paired_x_updates_bitwise(inner):
+    """Inside a chunk of iterations the x update of every other iteration waits
+    for the next iteration, which applies both (the same multiply-adds in the
+    same order), with the waiting direction kept in a second buffer. After the
+    same 16 iterations, chunks of 1 (every update at once), 3 (odd chunks,
+    ending on an immediate update) and 8 must give bitwise the same solution.
+    Reliable updates and convergence are kept out of the way (delta and tol
+    tiny) until the final true residual; 3 right-hand sides."""
+    dims = (8, 8, 4, 4)
+    U = li.near_unity_gauge(dims, 77, 0.3)
+    bs = li.gaussian_spinors(dims, [78, 79, 80])
+    masses = [0.05, 0.2, 0.5]
+    ref = None
+    for ce in (1, 3, 8):
+        rc, xs, stats, _ = solve(U, masses, bs, INNER[inner], tol=1e-30, max_iter=16, delta=1e-30,
+                                 check_every=ce)
+        assert rc == w.WD_ERR_NOT_CONVERGED, stats
+        assert all(st["iters"] == 16 and st["reliable_updates"] == 1 for st in stats), stats
+        if ref is None:
+            ref = xs
+        else:
+            assert np.array_equal(xs, ref), f"check_every={ce}"
+
+
 def test_cg_multi_rhs_equals_alone():
     """Each right-hand side of a batch (own mass) gives bitwise the result it gets alone."""
     dims = (8, 8, 4, 4)
