@@ -480,6 +480,13 @@ int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, i
     else active.push(k);
   }
   int it = 0;
+  // Right-hand sides whose true residual was recomputed before the last chunk
+  // without the host waiting for it (refresh_it: the iterations then). The
+  // recompute leaves its scalars (kRrTrue, kFlag) to the next read; one that
+  // has converged keeps its FP64 x from then (the chunk only added to x_lo,
+  // which is never flushed again).
+  IdxList unread;
+  int refresh_it[kMaxRhs] = {};
   while (rc == WD_OK && active.n > 0 && it < prm.max_iter) {
     // iterations up to the next check (a multiple of check_every, or max_iter)
     const int n = std::min(prm.check_every - it % prm.check_every, prm.max_iter - it);
@@ -490,6 +497,24 @@ int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, i
     for (int i = 0; i < active.n; ++i) iters[active.k[i]] = it;
     const bool at_max = it >= prm.max_iter;
     if ((rc = read()) != WD_OK) break;
+    if (unread.n > 0) {
+      IdxList going;
+      for (int i = 0; i < active.n; ++i) {
+        const int k = active.k[i];
+        if (!unread.has(k)) {
+          going.push(k);
+          continue;
+        }
+        ++updates[k];
+        switch (cg_after_refresh(sc(k), prm.tol, false)) {
+          case kCgConverged: status[k] = WD_OK; iters[k] = refresh_it[k]; break;
+          case kCgFailed: status[k] = WD_ERR_NUMERIC; iters[k] = refresh_it[k]; break;
+          default: going.push(k); break;
+        }
+      }
+      active = going;
+      unread = IdxList{};
+    }
     IdxList refresh, keep;
     for (int i = 0; i < active.n; ++i) {
       const int k = active.k[i];
@@ -500,7 +525,23 @@ int solve_sync(const wd_gauge* ghi, const wd_gauge* glo, const double* masses, i
     }
     active = keep;
     if (refresh.n == 0) continue;
-    if ((rc = eng.refresh(refresh.set())) != WD_OK || (rc = read()) != WD_OK) break;
+    if ((rc = eng.refresh(refresh.set())) != WD_OK) break;
+    // A recompute that follows a drop of the iterated residual by delta, with
+    // no right-hand side claiming convergence and iterations left, almost
+    // never ends a solve: the next chunk goes out at once and its read brings
+    // the outcome (one wait for the device fewer per reliable update; a solve
+    // that did converge there has run one chunk for nothing)
+    bool wait = at_max;
+    for (int i = 0; i < refresh.n; ++i) {
+      const double* c = sc(refresh.k[i]);
+      if (c[kRr] <= prm.tol * prm.tol * c[kB2]) wait = true;
+    }
+    if (!wait) {
+      unread = refresh;
+      for (int i = 0; i < refresh.n; ++i) refresh_it[refresh.k[i]] = it;
+      continue;
+    }
+    if ((rc = read()) != WD_OK) break;
     IdxList still;
     for (int i = 0; i < active.n; ++i) {
       const int k = active.k[i];
