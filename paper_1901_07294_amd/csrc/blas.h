@@ -84,6 +84,11 @@ hipError_t blas_update_p(void* p, const void* r, int prec, long n, long V, const
                          const double* rr, int nrr, double* scal, hipStream_t st);
 hipError_t blas_residual(void* r, const void* b, long n, long V, const RhsSet& set, double* partials,
                          double* scal, hipStream_t st);
+// Mixed precision true residual: lo (FP32 or FP16) = b - ax (ax holds A x,
+// FP64) rounded, with <r, r> of the FP64 values recorded as blas_residual
+// does; the FP64 residual itself is not stored.
+hipError_t blas_residual_demote(void* lo, const void* b, const void* ax, int prec, long n, long nhi, long V,
+                                const RhsSet& set, double* partials, double* scal, hipStream_t st);
 // lo (FP32 or FP16) = hi (FP64)
 hipError_t blas_demote(void* lo, const void* hi, int prec, long n, long nhi, long V, const RhsSet& set,
                        hipStream_t st);

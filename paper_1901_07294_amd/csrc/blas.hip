@@ -396,6 +396,36 @@ __global__ __launch_bounds__(kThreads) void demote_kernel(float4* __restrict__ l
   }
 }
 
+// lo = FP32(b - ax) over FP32 elements, with partial |b - ax|^2 of the FP64
+// values (the mixed solver's true residual: its FP64 form is not kept)
+__global__ __launch_bounds__(kThreads) void residual_demote_kernel(float4* __restrict__ lo,
+                                                                   const double2* __restrict__ b,
+                                                                   const double2* __restrict__ ax, long n,
+                                                                   long nhi, long V, RhsSet set,
+                                                                   double* __restrict__ partials) {
+  const int k = set.idx[blockIdx.y];
+  float4* lk = lo + k * n;
+  const double2* bk = b + k * nhi;
+  const double2* ak = ax + k * nhi;
+  double s = 0.0;
+  for (long e = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; e < n;
+       e += static_cast<long>(gridDim.x) * kThreads) {
+    const long blk = e / (6 * kLayoutBlock);
+    const long j = (e / kLayoutBlock) % 6;
+    const long lane = e % kLayoutBlock;
+    const long h0 = (blk * 12 + 2 * j) * kLayoutBlock + lane;
+    const double2 b0 = bk[h0], b1 = bk[h0 + kLayoutBlock];
+    const double2 a0 = ak[h0], a1 = ak[h0 + kLayoutBlock];
+    const double2 r0 = make_double2(b0.x - a0.x, b0.y - a0.y);
+    const double2 r1 = make_double2(b1.x - a1.x, b1.y - a1.y);
+    lk[e] = make_float4(static_cast<float>(r0.x), static_cast<float>(r0.y), static_cast<float>(r1.x),
+                        static_cast<float>(r1.y));
+    if (real_site<6>(e, V)) s += norm2(r0) + norm2(r1);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void copy_kernel(T* __restrict__ dst, const T* __restrict__ src,
                                                         long n, RhsSet set) {
@@ -530,6 +560,33 @@ __global__ __launch_bounds__(kThreads) void demote_half_kernel(h8* __restrict__ 
     }
     store_half_site(lo + k * units, i, v);
   }
+}
+
+// lo = FP16(b - ax) (components rounded to FP32, then quantised per site),
+// with partial |b - ax|^2 of the FP64 values
+__global__ __launch_bounds__(kThreads) void residual_demote_half_kernel(h8* __restrict__ lo,
+                                                                        const double2* __restrict__ b,
+                                                                        const double2* __restrict__ ax,
+                                                                        long units, long nhi, long V,
+                                                                        RhsSet set,
+                                                                        double* __restrict__ partials) {
+  const int k = set.idx[blockIdx.y];
+  const double2* bk = b + k * nhi;
+  const double2* ak = ax + k * nhi;
+  double s = 0.0;
+  WD_SITE_LOOP(i, V) {
+    cx<float> v[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const double2 bt = bk[pidx(i, c, 12, V)], at = ak[pidx(i, c, 12, V)];
+      const double2 t = make_double2(bt.x - at.x, bt.y - at.y);
+      s += norm2(t);
+      v[c] = {static_cast<float>(t.x), static_cast<float>(t.y)};
+    }
+    store_half_site(lo + k * units, i, v);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
 }
 
 #undef WD_SITE_LOOP
@@ -699,6 +756,25 @@ hipError_t blas_residual(void* r, const void* b, long n, long V, const RhsSet& s
   const dim3 g = grid(n, set.n);
   residual_kernel<<<g, kThreads, 0, st>>>(static_cast<double2*>(r), static_cast<const double2*>(b), n,
                                           V, set, partials);
+  finalize_kernel<<<set.n, kThreads, 0, st>>>(partials, static_cast<int>(g.x), set, kFinTrueRr, scal);
+  return hipGetLastError();
+}
+
+hipError_t blas_residual_demote(void* lo, const void* b, const void* ax, int prec, long n, long nhi, long V,
+                                const RhsSet& set, double* partials, double* scal, hipStream_t st) {
+  dim3 g;
+  if (prec == WD_FP32) {
+    g = grid(n, set.n);
+    residual_demote_kernel<<<g, kThreads, 0, st>>>(static_cast<float4*>(lo), static_cast<const double2*>(b),
+                                                   static_cast<const double2*>(ax), n, nhi, V, set, partials);
+  } else if (prec == WD_FP16) {
+    g = grid(V, set.n);
+    residual_demote_half_kernel<<<g, kThreads, 0, st>>>(static_cast<h8*>(lo), static_cast<const double2*>(b),
+                                                        static_cast<const double2*>(ax), n, nhi, V, set,
+                                                        partials);
+  } else {
+    return hipErrorInvalidValue;
+  }
   finalize_kernel<<<set.n, kThreads, 0, st>>>(partials, static_cast<int>(g.x), set, kFinTrueRr, scal);
   return hipGetLastError();
 }

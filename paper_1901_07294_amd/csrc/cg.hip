@@ -259,13 +259,14 @@ int CgEngine::refresh(const RhsSet& set) {
   if (rc == WD_OK) rc = apply_q(ghi_, m, set, x_, at(ws_, lay_.e_hi), at(ws_, lay_.t_hi), "cg: Q x");
   if (rc == WD_OK)
     rc = apply_q(ghi_, m, set, at(ws_, lay_.t_hi), at(ws_, lay_.e_hi), at(ws_, lay_.r_hi), "cg: Q Q x");
-  if (rc == WD_OK)
-    rc = launch_status(blas_residual(at(ws_, lay_.r_hi), b_, nhi_, V_, set, partials_, scal_, st_),
-                       "cg: b - A x");
-  if (rc == WD_OK && inner_ != WD_FP64)
-    rc = launch_status(blas_demote(at(ws_, lay_.r), at(ws_, lay_.r_hi), inner_, nlo_, nhi_, V_, set, st_),
-                       "cg: demote");
-  return rc;
+  if (rc != WD_OK) return rc;
+  if (inner_ == WD_FP64)  // r_hi is the iteration's residual
+    return launch_status(blas_residual(at(ws_, lay_.r_hi), b_, nhi_, V_, set, partials_, scal_, st_),
+                         "cg: b - A x");
+  // mixed: only the inner-precision residual is kept (r_hi holds A x)
+  return launch_status(blas_residual_demote(at(ws_, lay_.r), b_, at(ws_, lay_.r_hi), inner_, nlo_, nhi_, V_,
+                                            set, partials_, scal_, st_),
+                       "cg: b - A x, demoted");
 }
 
 int CgEngine::fetch_scalars(double* host) const {
