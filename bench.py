@@ -49,13 +49,14 @@ def compulsory_bytes(prec: str, c12: bool) -> int:
 TRAFFIC = {
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (copy-calibrated KiB per dispatch), measured for
     # the kernel code hashed below, per launch "tb,gw,group,rb" the bytes belong to
-    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "40357ec387863f3b", "launches": {
-        "32,1,32,1": 2260103712,    # 906,958.3 / 393,216.0
-        "16,1,64,1": 2379502656}},  # 965,258.5 / 393,216.0
-    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "40357ec387863f3b", "launches": {
-        "16,1,64,1": 1123403296}},  # 450,232.8 / 196,608.0
-    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "40357ec387863f3b", "launches": {
-        "4,1,256,1": 622496448}},   # 250,705.3 / 106,496.0
+    "wilson_dslash_32x32x32x64_fp64": {"source_sha": "f8e8833d29f40acb", "launches": {
+        "32,1,32,1": 2211276800}},  # 883,117 / 393,216
+    "wilson_dslash_32x32x32x64_fp64_c12": {"source_sha": "f8e8833d29f40acb", "launches": {
+        "32,1,32,1": 1778633728}},  # 671,843 / 393,261
+    "wilson_dslash_32x32x32x64_fp32": {"source_sha": "f8e8833d29f40acb", "launches": {
+        "16,1,64,1": 1115131904}},  # 446,191 / 196,614
+    "wilson_dslash_32x32x32x64_fp16": {"source_sha": "f8e8833d29f40acb", "launches": {
+        "4,1,256,1": 618565632}},   # 248,786 / 106,496
 }
 KERNEL_SOURCES = ["paper_1901_07294_amd/csrc/dslash.hip", "paper_1901_07294_amd/csrc/stencil.h",
                   "paper_1901_07294_amd/csrc/fields.h", "paper_1901_07294_amd/csrc/cplx.h"]
