@@ -538,9 +538,11 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
                 base = [li.gaussian_spinor(d, 5200 + 10 * i + k) for k in range(4)]
                 bs = np.stack([base[k % 4] for k in range(nrhs_max)])
                 pool = packer.pack(bs, nrhs=nrhs_max)   # shared, read-only right-hand sides
-                small = d[0] * d[1] * d[2] * d[3] <= 16 ** 4
-                lat.append({"dims": d, "U": U if small else None, "gid": gid, "packer": packer,
-                            "pool": pool, "b": bs if small else None})
+                del bs
+                # the oracle checks results of 8^4 and 16^4 requests, and one of 24^3x48
+                checked = d[0] * d[1] * d[2] * d[3] <= 24 ** 3 * 48
+                lat.append({"dims": d, "U": U if checked else None, "gid": gid, "packer": packer,
+                            "pool": pool, "base": base if checked else None})
         return lat
 
     def draw(lat, max_rhs):
@@ -548,22 +550,26 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
         nrhs = int(rng.integers(1, max_rhs + 1))
         return i, list(rng.uniform(0.05, 0.5, nrhs))
 
-    def run_stream(srv, lat, reqs, arrivals, max_live=80, keep=12):
+    def run_stream(srv, lat, reqs, arrivals, max_live=80, keep=12, keep_mid=0):
         """Submits reqs[k] = (pool index, masses) at arrivals[k] (s; None = as
         soon as fewer than max_live requests are in flight); returns
         {ticket: (rc, res, (pool index, masses, x or None))} and the makespan.
         Solutions are kept for the first `keep` finished 8^4 / 16^4 requests
-        only (the oracle's sample); the others' buffers are released."""
+        and the first `keep_mid` 24^3 x 48 ones (the oracle's sample); the
+        others' buffers are released."""
         live, done = {}, {}
-        kept = [0]
+        kept = {"small": 0, "mid": 0}
 
         def poll():
             for t in list(live):
                 rc, res = w.cg_poll(srv, t)
                 if rc != w.WD_PENDING:
                     i, m, x = live.pop(t)
-                    if lat[i]["U"] is not None and kept[0] < keep:
-                        kept[0] += 1
+                    kind = None
+                    if lat[i]["U"] is not None:
+                        kind = "small" if li.volume(lat[i]["dims"]) <= 16 ** 4 else "mid"
+                    if kind is not None and kept[kind] < (keep if kind == "small" else keep_mid):
+                        kept[kind] += 1
                     else:
                         x = None
                     done[t] = (rc, res, (i, m, x))
@@ -589,24 +595,27 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
             time.sleep(0.0005)
         return done, time.time() - t0
 
-    def worst_residual(lat, done, limit=12):
+    def worst_residual(lat, done, limit=12, mid=False):
         """Largest true residual the oracle recomputes over a sample of at most
         `limit` right-hand sides of the kept 8^4 and 16^4 solutions (smallest
-        lattice first)."""
+        lattice first); with mid, the true residual of the first right-hand
+        side of the kept 24^3 x 48 solution instead."""
         worst, checked = 0.0, 0
-        small = [v for v in done.values() if v[2][2] is not None]
-        small.sort(key=lambda v: li.volume(lat[v[2][0]]["dims"]))
-        for rc, res, (i, m, x) in small:
-            if checked >= limit:
+        kept = [v for v in done.values() if v[2][2] is not None and
+                (li.volume(lat[v[2][0]]["dims"]) > 16 ** 4) == mid]
+        kept.sort(key=lambda v: li.volume(lat[v[2][0]]["dims"]))
+        for rc, res, (i, m, x) in kept:
+            if checked >= (1 if mid else limit):
                 break
             L = lat[i]
             xs = L["packer"].unpack(x, nrhs=len(m))
             xs = xs if len(m) > 1 else xs[None]
-            for k in range(min(len(m), limit - checked)):
-                r = L["b"][k] - oracle.normal_op(L["U"], m[k], xs[k])
-                worst = max(worst, float(np.linalg.norm(r) / np.linalg.norm(L["b"][k])))
+            for k in range(min(len(m), (1 if mid else limit) - checked)):
+                b = L["base"][k % 4]
+                r = b - oracle.normal_op(L["U"], m[k], xs[k])
+                worst = max(worst, float(np.linalg.norm(r) / np.linalg.norm(b)))
                 checked += 1
-        return worst
+        return worst if checked or not mid else None
 
     def pct(v, q):
         return round(float(np.percentile(v, q)) * 1e3, 2)
@@ -623,7 +632,7 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
         reqs = [draw(lat, nrhs_max) for _ in range(n_req)]
         gaps = rng.exponential(1.0, n_req)  # unit-rate Poisson gaps, scaled per level
         nrhs_total = sum(len(m) for _, m in reqs)
-        done, makespan = run_stream(srv, lat, reqs, [None] * n_req)
+        done, makespan = run_stream(srv, lat, reqs, [None] * n_req, keep_mid=1)
         capacity = n_req / makespan
         print(f"[bench] serving capacity {capacity:.2f} req/s", file=sys.stderr, flush=True)
         out["requests"] = n_req
@@ -632,6 +641,8 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
         out["capacity_rhs_solves_per_s"] = round(nrhs_total / makespan, 2)
         out["levels"] = []
         worst = worst_residual(lat, done)
+        # one 24^3 x 48 right-hand side, recomputed in full by the oracle (~5 s)
+        out["oracle_true_rel_residual_24x24x24x48"] = worst_residual(lat, done, mid=True)
         for load in loads:
             arrivals = list(np.cumsum(gaps / (load * capacity)))
             done, wall = run_stream(srv, lat, reqs, arrivals)
