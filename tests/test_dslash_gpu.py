@@ -143,7 +143,7 @@ def production():
 
 
 @pytest.mark.parametrize("c12", [False, True], ids=["full", "c12"])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
 def test_production_lattice_full_field(production, prec, c12):
     """Every site of 32^3 x 64 against the oracle, in the launch the benchmark
     times: the key is tuned first (the tuner keeps only choices whose output
@@ -160,8 +160,10 @@ def test_production_lattice_full_field(production, prec, c12):
     w.dslash_apply(g.handle, 0.1, src, dst, g.prec)
     out = g.unpack(dst)
     assert rel(out, ref) <= TOL[PRECS[prec]]
+    # every site: its largest error against its largest component (FP16 storage
+    # rounds each input site to 11 bits of its own largest component)
     site_err = np.abs(out - ref).max(axis=(-2, -1)) / np.abs(ref).max(axis=(-2, -1))
-    assert float(site_err.max()) <= 1e3 * TOL[PRECS[prec]]
+    assert float(site_err.max()) <= (10 if prec == "fp16" else 1e3) * TOL[PRECS[prec]]
     # the second application is bitwise identical (no atomics, fixed order)
     dst2 = g.spinor()
     w.dslash_apply(g.handle, 0.1, src, dst2, g.prec)
