@@ -171,6 +171,27 @@ def test_production_lattice_full_field(production, prec, c12):
     assert torch.equal(dst, dst2)
 
 
+def test_links_beyond_4_gib():
+    """48^3 x 72 in FP64 (7,962,624 sites): the packed links take 4.59 GB, more
+    than 32-bit buffer offsets reach, so the operator must read them through
+    plain pointers. Sampled sites, among them the last ones (whose t links lie
+    beyond 4 GiB in the packed field), against the oracle."""
+    dims = (48, 48, 48, 72)
+    assert w.wd_gauge_bytes(dims, w.WD_FP64, 0) > 1 << 32
+    print(f"case dims={dims} fp64: links beyond 4 GiB", flush=True)
+    U = li.random_gauge(dims, li.seed_gauge(5))
+    psi = li.gaussian_spinor(dims, li.seed_spinor(5))
+    g = DeviceGauge(U, w.WD_FP64)
+    src = g.pack(psi)
+    dst = g.spinor()
+    w.dslash_apply(g.handle, 0.1, src, dst, w.WD_FP64)
+    out = g.unpack(dst).reshape(-1, 4, 3)
+    V = li.volume(dims)
+    rng = np.random.default_rng(55)
+    sites = np.concatenate([rng.choice(V, 2000, replace=False), np.arange(64), V - 1 - np.arange(64)])
+    assert rel(out[sites], oracle.dslash_sites(U, psi, 0.1, sites)) <= TOL[w.WD_FP64]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_pack_roundtrip_exact(prec):
     dims = (5, 3, 7, 4)
