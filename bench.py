@@ -550,15 +550,22 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
         nrhs = int(rng.integers(1, max_rhs + 1))
         return i, list(rng.uniform(0.05, 0.5, nrhs))
 
-    def run_stream(srv, lat, reqs, arrivals, max_live=80, keep=12, keep_mid=0):
+    def run_stream(srv, lat, reqs, arrivals, max_live=80, keep=12, keep_mid=0, max_live_bytes=96 << 30):
         """Submits reqs[k] = (pool index, masses) at arrivals[k] (s; None = as
         soon as fewer than max_live requests are in flight); returns
-        {ticket: (rc, res, (pool index, masses, x or None))} and the makespan.
-        Solutions are kept for the first `keep` finished 8^4 / 16^4 requests
-        and the first `keep_mid` 24^3 x 48 ones (the oracle's sample); the
-        others' buffers are released."""
+        {ticket: (rc, res, (pool index, masses, x or None))}, the makespan and
+        how many submissions waited for client memory. The solutions' buffers
+        (the client's) in flight stay under max_live_bytes: a submission that
+        would pass it waits for earlier requests to finish. Solutions are kept
+        for the first `keep` finished 8^4 / 16^4 requests and the first
+        `keep_mid` 24^3 x 48 ones (the oracle's sample); the others' buffers
+        are released."""
         live, done = {}, {}
         kept = {"small": 0, "mid": 0}
+        held = [0]
+
+        def live_bytes():
+            return sum(v[2].numel() for v in live.values())
 
         def poll():
             for t in list(live):
@@ -581,6 +588,12 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
             while (a is not None and time.time() - t0 < a) or (a is None and len(live) >= max_live):
                 poll()
                 time.sleep(0.0005)
+            need = w.wd_spinor_bytes(lat[i]["dims"], w.WD_FP64, len(m))
+            if live and live_bytes() + need > max_live_bytes:
+                held[0] += 1
+                while live and live_bytes() + need > max_live_bytes:
+                    poll()
+                    time.sleep(0.0005)
             x = lat[i]["packer"].spinor(len(m))
             t = w.cg_submit(srv, lat[i]["gid"], m, lat[i]["pool"], x, tol=1e-10)
             live[t] = (i, m, x)
@@ -593,7 +606,7 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
                 note += 30
             poll()
             time.sleep(0.0005)
-        return done, time.time() - t0
+        return done, time.time() - t0, held[0]
 
     def worst_residual(lat, done, limit=12, mid=False):
         """Largest true residual the oracle recomputes over a sample of at most
@@ -632,20 +645,21 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
         reqs = [draw(lat, nrhs_max) for _ in range(n_req)]
         gaps = rng.exponential(1.0, n_req)  # unit-rate Poisson gaps, scaled per level
         nrhs_total = sum(len(m) for _, m in reqs)
-        done, makespan = run_stream(srv, lat, reqs, [None] * n_req, keep_mid=1)
+        done, makespan, held = run_stream(srv, lat, reqs, [None] * n_req, keep_mid=1)
         capacity = n_req / makespan
         print(f"[bench] serving capacity {capacity:.2f} req/s", file=sys.stderr, flush=True)
         out["requests"] = n_req
         out["rhs_per_request_mean"] = round(nrhs_total / n_req, 2)
         out["capacity_req_per_s"] = round(capacity, 3)
         out["capacity_rhs_solves_per_s"] = round(nrhs_total / makespan, 2)
+        out["capacity_submissions_held_for_client_memory"] = held
         out["levels"] = []
         worst = worst_residual(lat, done)
         # one 24^3 x 48 right-hand side, recomputed in full by the oracle (~5 s)
         out["oracle_true_rel_residual_24x24x24x48"] = worst_residual(lat, done, mid=True)
         for load in loads:
             arrivals = list(np.cumsum(gaps / (load * capacity)))
-            done, wall = run_stream(srv, lat, reqs, arrivals)
+            done, wall, held = run_stream(srv, lat, reqs, arrivals)
             lat_s = np.array([res["t_done"] - res["t_submit"] for rc, res, _ in done.values()])
             wait_s = np.array([res["t_start"] - res["t_submit"] for rc, res, _ in done.values()])
             out["levels"].append({
@@ -653,7 +667,8 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
                 "ok": int(sum(rc == w.WD_OK for rc, _, _ in done.values())),
                 "req_per_s": round(n_req / wall, 3), "rhs_solves_per_s": round(nrhs_total / wall, 2),
                 "p50_ms": pct(lat_s, 50), "p90_ms": pct(lat_s, 90), "p99_ms": pct(lat_s, 99),
-                "queue_wait_p50_ms": pct(wait_s, 50), "queue_wait_p99_ms": pct(wait_s, 99)})
+                "queue_wait_p50_ms": pct(wait_s, 50), "queue_wait_p99_ms": pct(wait_s, 99),
+                "submissions_held_for_client_memory": held})
             worst = max(worst, worst_residual(lat, done))
             lv = out["levels"][-1]
             print(f"[bench] serving load {load}: p50 {lv['p50_ms']} ms, p99 {lv['p99_ms']} ms",
@@ -675,7 +690,7 @@ def bench_serve(torch, w, li, DeviceGauge, n_req=80, loads=(0.5, 0.8, 0.95), see
                              n_streams=2)
     try:
         lat = make_pool(srv, small_sizes, 2)
-        done, wall = run_stream(srv, lat, [draw(lat, 4) for _ in range(16)], [None] * 16)
+        done, wall, _ = run_stream(srv, lat, [draw(lat, 4) for _ in range(16)], [None] * 16)
         wait_s = np.array([res["t_start"] - res["t_submit"] for rc, res, _ in done.values()])
         info = w.wd_server_info(srv)
         out["small_arena"] = {
